@@ -1,0 +1,193 @@
+/*
+ * gravidy_hip.h — C ABI of the MI355X (gfx950) Hermite-4 block-time-step
+ * direct-summation N-body library with Plummer softening, after GraviDy
+ * (arXiv:1702.00440).
+ *
+ * The library evaluates, on one GPU, the steps of the paper's integration
+ * scheme (Sec. 2.4, the numbered step list): the O(N^2) initial force and
+ * energy, the search for the active particles of a block step, the
+ * prediction of all particles, the O(N_act * N) force (acceleration, Eq. (3),
+ * and its time derivative, the jerk), and the Hermite correction with the new
+ * block time step. Every step runs on the device; the host only sequences
+ * launches.
+ *
+ * Conventions shared by every call:
+ *   - Return value: gd_status, 0 (GD_OK) on success, negative on error. No call
+ *     throws or aborts. gd_last_error() gives a message for the last failure.
+ *   - Units: G = 1 (N-body units, Sec. 3.1).
+ *   - Array arguments are DEVICE pointers (memory on the GPU the context runs
+ *     on) unless marked "host". Vectors are row-major (n, 3) arrays of
+ *     double: element (i, d) at index 3 * i + d. The caller owns every array;
+ *     the library reads or writes it during the call (in stream order) and
+ *     keeps no reference after the call's work has run.
+ *   - Device memory: the library never allocates device memory. The caller
+ *     provides one workspace of at least gd_workspace_bytes() bytes, aligned
+ *     to 256 bytes, which the context owns until gd_destroy.
+ *   - Streams: all device work is enqueued on the stream given to gd_init
+ *     (a hipStream_t; NULL means the default stream). Calls that return host
+ *     values synchronise that stream; the others return once work is queued.
+ *   - Threads: one context is driven by one host thread at a time. Distinct
+ *     contexts may be used concurrently.
+ *   - Time: block time steps are dt_max / 2^k (k >= 0), clamped at dt_min;
+ *     both must be powers of two. Times are kept exactly as integer multiples
+ *     of dt_min; log2(dt_max / dt_min) must be at most 40.
+ */
+#ifndef GRAVIDY_HIP_H
+#define GRAVIDY_HIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gd_ctx gd_ctx; /* opaque; host-side state owned by the library */
+
+typedef enum {
+  GD_OK = 0,
+  GD_EINVAL = -1,     /* an argument is out of its documented range */
+  GD_ENOMEM = -2,     /* the workspace is smaller than gd_workspace_bytes() */
+  GD_EHIP = -3,       /* a HIP runtime call failed; see gd_last_error() */
+  GD_ESTATE = -4,     /* the call is not valid in the context's current phase */
+  GD_ENONFINITE = -5  /* a non-finite acceleration or jerk was produced */
+} gd_status;
+
+typedef struct {
+  double eta;     /* time-step accuracy parameter (Sec. 3.2; paper default 0.01), > 0 */
+  double eps;     /* Plummer softening length (Eq. (3); paper default 1e-4); 0 or >= 1e-30 */
+  double dt_max;  /* largest block step, a power of two (e.g. 0.125) */
+  double dt_min;  /* smallest block step, a power of two <= dt_max (e.g. 2^-22) */
+  int32_t flags;  /* reserved, must be 0 */
+} gd_params;
+
+typedef struct {
+  double t;                   /* current block time of the context */
+  int64_t block_steps;        /* block steps taken since gd_init / gd_set_state */
+  int64_t particle_steps;     /* sum of N_act over those steps */
+  int64_t pair_interactions;  /* sum of N_act * N over those steps (self pair counted) */
+  int64_t dtmin_clamps;       /* times a step was clamped at dt_min */
+  double e0;                  /* energy at gd_init (kinetic + softened potential) */
+  double e;                   /* energy at the last synchronised time gd_step_to reached */
+} gd_stats;
+
+/*
+ * Bytes of device workspace a context for n particles needs (n >= 2).
+ * Host-only; no device work. p may be NULL (the size depends only on n).
+ */
+gd_status gd_workspace_bytes(int64_t n, const gd_params* p, size_t* bytes);
+
+/*
+ * Create a context and compute the initial state (Sec. 2.4, steps 1-3):
+ * masses m[n], positions x[n][3] and velocities v[n][3] (device arrays, copied
+ * in) at t = 0; the O(N^2) initial acceleration and jerk of every particle;
+ * the initial block step of each particle from dt* = eta |a| / |jerk| (the
+ * largest dt_max / 2^k <= dt*, clamped at dt_min); the initial energy (read
+ * by gd_stats as e0). Synchronises the stream.
+ * Errors: GD_EINVAL for n < 2, a NULL pointer, eta <= 0, eps outside
+ * {0} U [1e-30, inf), dt_max/dt_min not powers of two or dt_min > dt_max,
+ * log2(dt_max/dt_min) > 40, or non-finite m/x/v or m < 0 (checked on the
+ * device); GD_ENOMEM if ws_bytes is too small; GD_EHIP on HIP failure. On
+ * error *ctx is NULL.
+ */
+gd_status gd_init(gd_ctx** ctx, const gd_params* p, int64_t n, const double* m, const double* x,
+                  const double* v, void* workspace, size_t ws_bytes, void* hip_stream);
+
+/*
+ * Prediction of all particles (Sec. 2.4, steps 5 and 7(a)).
+ * t == NULL: find the next block time t_next (the earliest t_i + dt_i),
+ * mark the active particles (t_i + dt_i == t_next), and predict every particle
+ * to t_next with the third-order Taylor series (x, v, a, jerk at its own t_i).
+ * t != NULL (host): predict every particle to the time *t, with no active set
+ * (for diagnostics; gd_force then needs an explicit index list).
+ * Queues work only. Errors: GD_ESTATE if nothing is left to do (never in
+ * practice: some particle is always due), GD_EHIP.
+ */
+gd_status gd_predict(gd_ctx* c, const double* t);
+
+/*
+ * Softened acceleration (Eq. (3)) and jerk (its time derivative) of a set of
+ * particles from all n particles, on the predicted state of the last
+ * gd_predict (Sec. 2.4 step 7(c); Sec. 2.5). The self pair is excluded.
+ * idx == NULL: the active set of the last gd_predict(NULL); n_act is ignored
+ * and acc/jerk, if given, must hold n rows (the first N_act rows are written,
+ * in the order of gd_active).
+ * idx != NULL: n_act device int32 indices in [0, n) (repeats allowed).
+ * acc, jerk: device (n_act, 3) outputs, or NULL to keep the result internal
+ * (as gd_correct needs it). Queues work only.
+ * Errors: GD_ESTATE before any gd_predict, or idx == NULL after gd_predict(t);
+ * GD_EINVAL for n_act < 0 or > n; GD_EHIP.
+ */
+gd_status gd_force(gd_ctx* c, const int32_t* idx, int64_t n_act, double* acc, double* jerk);
+
+/*
+ * Active set of the last gd_predict(NULL): writes N_act device int32 indices
+ * to idx (capacity n; may be NULL) and N_act to *n_act (host). Synchronises.
+ * The order of the list is unspecified; results never depend on it.
+ */
+gd_status gd_active(gd_ctx* c, int32_t* idx, int64_t* n_act);
+
+/*
+ * Correction of the active set (Sec. 2.4 step 7(d)): fourth-order Hermite
+ * corrector from the old and new acceleration and jerk, new block step from
+ * the Aarseth criterion with eta (Sec. 3.2), and the move of the active
+ * particles to t_next. Queues work only.
+ * Errors: GD_ESTATE unless the last calls were gd_predict(NULL) then
+ * gd_force(NULL, ...); GD_EHIP.
+ */
+gd_status gd_correct(gd_ctx* c);
+
+/*
+ * Integrate from the current time to t_end (host value, a multiple of dt_max
+ * not before the current time) by repeated block steps (predict, force,
+ * correct). At every multiple of dt_max all particles are synchronised; the
+ * energy is computed there (kept as stats.e). st (host, may be NULL)
+ * receives the statistics. Synchronises.
+ * Errors: GD_EINVAL for a bad t_end; GD_ESTATE after a gd_predict not
+ * followed by gd_correct; GD_ENONFINITE; GD_EHIP.
+ */
+gd_status gd_step_to(gd_ctx* c, double t_end, gd_stats* st);
+
+/*
+ * Energy of the synchronised state, Eq. (2) with G = 1: ekin = 1/2 sum m v^2;
+ * epot = -sum_{i<j} m_i m_j / sqrt(|r_ij|^2 + eps^2) (softened; the quantity
+ * the softened dynamics conserve); epot_unsoft (may be NULL) the same with
+ * eps = 0 as printed in Eq. (2). Host outputs. Synchronises.
+ * Errors: GD_ESTATE if the particles are not all at the same time (only
+ * after gd_init, gd_set_state or gd_step_to they are); GD_EHIP.
+ */
+gd_status gd_energy(gd_ctx* c, double* ekin, double* epot, double* epot_unsoft);
+
+/*
+ * Copy the particle state out: x, v, a (acceleration), jerk as device
+ * (n, 3) arrays at each particle's own time; t_i and dt_i as device double[n];
+ * *t_now (host) the current block time. Any pointer may be NULL.
+ * Synchronises.
+ */
+gd_status gd_get_state(gd_ctx* c, double* x, double* v, double* a, double* jerk, double* t_i,
+                       double* dt_i, double* t_now);
+
+/*
+ * Replace the particle state (same layout as gd_get_state; all pointers
+ * required, t_now host). Valid states: dt_i a power of two in
+ * [dt_min, dt_max], t_i a multiple of dt_i, t_i <= t_now < t_i + dt_i, every
+ * value finite. Masses are kept. Statistics restart from zero. Synchronises.
+ * Errors: GD_EINVAL for an invalid state (checked on the device); GD_EHIP.
+ */
+gd_status gd_set_state(gd_ctx* c, const double* x, const double* v, const double* a,
+                       const double* jerk, const double* t_i, const double* dt_i, double t_now);
+
+/* Statistics (host output). Synchronises. */
+gd_status gd_stats_get(gd_ctx* c, gd_stats* st);
+
+/* Free the host-side context (not the workspace, which the caller owns). NULL is a no-op. */
+void gd_destroy(gd_ctx* c);
+
+/* Message for the last failing call on c (c may be NULL: then the last gd_init failure). */
+const char* gd_last_error(const gd_ctx* c);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GRAVIDY_HIP_H */

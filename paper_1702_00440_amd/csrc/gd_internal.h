@@ -1,0 +1,149 @@
+// Internal declarations shared by the kernels (gd_kernels.hip) and the C ABI
+// runtime (gd_api.hip). Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gd {
+
+// Launch geometry. Every kernel runs 256-lane workgroups (4 wave64s).
+constexpr int kBlock = 256;
+// j particles staged per LDS tile.
+constexpr int kTileJ = 256;
+// i particles held per lane by the force kernel.
+constexpr int kIPerLane = 2;
+// Work items the force decomposition aims for (about 4 workgroups per CU).
+constexpr int kTargetItems = 1024;
+// Fixed force grid: workgroups loop over items beyond it.
+constexpr int kForceGrid = 2048;
+// A lane of the split-j layout keeps at least this many j per slice.
+constexpr int kMinJPerLane = 16;
+// Energy: fixed grid of slice items.
+constexpr int kEnergyGrid = 1024;
+// Maximum block-step level (dt = dt_max / 2^level).
+constexpr int kMaxLevels = 41;
+
+// Predictor modes.
+enum : int { kPredAuto = 0, kPredAll = 1, kPredExplicit = 2 };
+
+// Device-resident scheduling and bookkeeping record (lives in the workspace).
+struct Sched {
+  long long t_now;   // current block time, in dt_min ticks
+  long long t_next;  // block time of the step in flight
+  long long t_end;   // steps whose t_next would exceed this are skipped
+  int n_act;         // active particles of the step in flight
+  int kthr;          // a particle is active when its level >= kthr
+  int done;          // 1: the step in flight is skipped (t_end reached)
+  int cnt;           // compaction counter of the active list
+  int nonfinite;     // set when a non-finite force or jerk is seen
+  int bad_input;     // set by input / state validation
+  long long block_steps, particle_steps, pairs, clamps;
+  int hist[kMaxLevels + 1];  // particles per level
+};
+
+// Decomposition of one force launch over (i tile, j slice) items.
+//   lj   : log2 of the lanes sharing one i (LJ = 1 << lj, 1..64, in one wave)
+//   it   : i particles per workgroup tile = (kBlock >> lj) * kIPerLane
+//   nit  : number of i tiles
+//   s    : number of j slices; item = itile * s + slice
+//   len  : j particles per slice
+struct Plan {
+  int lj, it, nit, s, len, items;
+};
+
+// The plan depends only on (n_act, n): every kernel that needs it recomputes
+// it, so the force kernel and the reduction inside the corrector agree.
+__host__ __device__ inline Plan make_plan(int n_act, int n) {
+  Plan p;
+  int max_s = (n + kTileJ - 1) / kTileJ;
+  if (max_s < 1) max_s = 1;
+  int lj = 0;
+  for (;;) {
+    int it = (kBlock >> lj) * kIPerLane;
+    int nit = (n_act + it - 1) / it;
+    if (nit < 1) nit = 1;
+    int s = kTargetItems / nit;
+    if (s >= 8) s &= ~7;  // slice index then follows blockIdx % 8, i.e. the XCD
+    if (s > max_s) s = max_s;
+    if (s < 1) s = 1;
+    int len = (n + s - 1) / s;
+    bool enough = nit * s >= kTargetItems;
+    bool last = lj == 6 || (len >> (lj + 1)) < kMinJPerLane;
+    if (enough || last) {
+      p.lj = lj;
+      p.it = it;
+      p.nit = nit;
+      p.s = s;
+      p.len = len;
+      p.items = nit * s;
+      return p;
+    }
+    ++lj;
+  }
+}
+
+// Rows of the partial-force buffer a context of n particles needs: for every
+// plan, s * n_act <= s * nit * it <= max(nit, kTargetItems) * it.
+inline long long partial_rows(long long n) {
+  return n + (long long)kBlock * kIPerLane + (long long)kTargetItems * kBlock * kIPerLane;
+}
+
+// Energy decomposition: items are (i tile of kBlock, j slice).
+struct EPlan {
+  int nit, s, len, items;
+};
+__host__ __device__ inline EPlan make_eplan(int n) {
+  EPlan e;
+  e.nit = (n + kBlock - 1) / kBlock;
+  int max_s = (n + kTileJ - 1) / kTileJ;
+  int s = kEnergyGrid / e.nit;
+  if (s > max_s) s = max_s;
+  if (s < 1) s = 1;
+  e.s = s;
+  e.len = (n + s - 1) / s;
+  e.items = e.nit * s;
+  return e;
+}
+
+// Device pointers of one context, carved from the caller's workspace.
+struct Dev {
+  Sched* sc;
+  double* m;
+  double *x, *y, *z, *vx, *vy, *vz;        // corrected state at t_i
+  double *ax, *ay, *az, *jx, *jy, *jz;     // acceleration, jerk at t_i
+  double *px, *py, *pz, *pvx, *pvy, *pvz;  // predicted j stream
+  long long* tick;                         // t_i in dt_min ticks
+  int* lev;                                // dt_i = dt_max / 2^lev
+  int* active;                             // active list (positions 0..n_act-1)
+  double* part;                            // [s][6][n_act] partial forces
+  double* ebuf;                            // energy partials [kEnergyGrid][3] + result [3]
+};
+
+struct Consts {
+  int n;
+  int kmax;        // log2(dt_max / dt_min)
+  double dt_min, dt_max, eta, eps2;
+};
+
+// Launchers (gd_kernels.hip). Each returns the hipGetLastError() of its launch.
+hipError_t launch_load(const Dev& d, const Consts& c, const double* m, const double* x,
+                       const double* v, hipStream_t s);
+hipError_t launch_predict(const Dev& d, const Consts& c, int mode, double t_explicit, hipStream_t s);
+hipError_t launch_force(const Dev& d, const Consts& c, hipStream_t s);
+hipError_t launch_correct(const Dev& d, const Consts& c, hipStream_t s);
+hipError_t launch_init_dt(const Dev& d, const Consts& c, hipStream_t s);
+hipError_t launch_energy(const Dev& d, const Consts& c, int unsoft, hipStream_t s);
+hipError_t launch_set_tend(const Dev& d, long long t_end, hipStream_t s);
+hipError_t launch_reset_sched(const Dev& d, long long t_now, hipStream_t s);
+hipError_t launch_set_active(const Dev& d, const Consts& c, const int32_t* idx, int n_act, hipStream_t s);
+hipError_t launch_gather_forces(const Dev& d, const Consts& c, int n_rows_max, double* acc,
+                                double* jerk, hipStream_t s);
+hipError_t launch_copy_active(const Dev& d, const Consts& c, int32_t* idx, hipStream_t s);
+hipError_t launch_get_state(const Dev& d, const Consts& c, double* x, double* v, double* a,
+                            double* jerk, double* t_i, double* dt_i, hipStream_t s);
+hipError_t launch_set_state(const Dev& d, const Consts& c, const double* x, const double* v,
+                            const double* a, const double* jerk, const double* t_i,
+                            const double* dt_i, long long t_now, hipStream_t s);
+
+}  // namespace gd

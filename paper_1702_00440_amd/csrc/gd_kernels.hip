@@ -1,0 +1,892 @@
+// HIP kernels for gfx950 (MI355X): the device side of the Hermite-4
+// block-time-step integrator with Plummer softening of GraviDy
+// (arXiv:1702.00440). Every step of the paper's integration scheme (Sec. 2.4,
+// numbered step list) runs here: prediction of all particles, the active-set
+// search, the O(N_act * N) acceleration and jerk, the Hermite corrector with
+// the Aarseth block time step, and the O(N^2) energy.
+//
+// Layout: structure-of-arrays FP64 in one caller-owned workspace (gd_api.hip
+// carves it). Times are integers in units of dt_min; a particle's step is
+// dt_max / 2^lev, i.e. 2^(kmax - lev) ticks.
+//
+// Determinism: no floating-point atomics anywhere. Every sum has a fixed
+// order that depends only on (n_act, n), never on scheduling or on the order
+// of the active list, so results are bitwise reproducible.
+
+#include "gd_internal.h"
+
+namespace gd {
+
+// ---------------------------------------------------------------------------
+// Pair arithmetic (FP64)
+// ---------------------------------------------------------------------------
+
+// 1/sqrt(s) to full FP64 accuracy. v_rsq_f64 alone is good to about 2^-24
+// (measured), so one third-order step follows: with e = 1 - s y^2,
+// y' = y (1 + e/2 + 3 e^2 / 8) is the Taylor series of y (1 - e)^(-1/2) and
+// leaves a relative error of about (5/16) e^3, far below 2^-53.
+__device__ __forceinline__ double rsqrt_fp64(double s) {
+  double y = __builtin_amdgcn_rsq(s);
+  double e = fma(-s, y * y, 1.0);
+  double p = fma(e, 0.375, 0.5);
+  return fma(y * e, p, y);
+}
+
+// Accumulators of one i particle: acceleration and jerk.
+struct Acc6 {
+  double ax, ay, az, jx, jy, jz;
+};
+
+// Contribution of particle j to particle i (Eq. (3) and its time derivative):
+//   r = x_j - x_i, w = v_j - v_i, s = r.r + eps^2, q = s^(-1/2)
+//   a    += m_j q^3 r
+//   jerk += m_j q^3 (w - 3 (r.w) q^2 r)
+__device__ __forceinline__ void pair_fp64(double xi, double yi, double zi, double vxi, double vyi,
+                                          double vzi, double xj, double yj, double zj, double vxj,
+                                          double vyj, double vzj, double mj, double eps2,
+                                          Acc6& A) {
+  const double dx = xj - xi, dy = yj - yi, dz = zj - zi;
+  const double dvx = vxj - vxi, dvy = vyj - vyi, dvz = vzj - vzi;
+  const double s = fma(dz, dz, fma(dy, dy, fma(dx, dx, eps2)));
+  const double rv = fma(dz, dvz, fma(dy, dvy, dx * dvx));
+  const double q = rsqrt_fp64(s);
+  const double q2 = q * q;
+  const double mq3 = (mj * q) * q2;
+  const double b3 = (rv * q2) * -3.0;
+  A.ax = fma(mq3, dx, A.ax);
+  A.ay = fma(mq3, dy, A.ay);
+  A.az = fma(mq3, dz, A.az);
+  const double wx = fma(b3, dx, dvx), wy = fma(b3, dy, dvy), wz = fma(b3, dz, dvz);
+  A.jx = fma(mq3, wx, A.jx);
+  A.jy = fma(mq3, wy, A.jy);
+  A.jz = fma(mq3, wz, A.jz);
+}
+
+__device__ __forceinline__ double shfl_xor_d(double v, int mask) { return __shfl_xor(v, mask, 64); }
+
+// ---------------------------------------------------------------------------
+// Force kernel: O(N_act * N) acceleration and jerk (Sec. 2.4 step 7(c), Sec. 2.5)
+// ---------------------------------------------------------------------------
+//
+// One launch shape serves every block size. The decomposition (make_plan)
+// is computed on the device from n_act, so a captured graph never needs the
+// host to know the block size:
+//   - items are (i tile, j slice) pairs; workgroups loop over items;
+//   - inside a workgroup, LJ = 2^lj consecutive lanes share the same i
+//     particles and split the slice's j between them (LJ = 1: pure
+//     i-parallel with LDS broadcast of j; LJ up to 64: split j inside a
+//     wave, for small active blocks);
+//   - each lane holds kIPerLane i particles, so one LDS read of j feeds
+//     several pair evaluations;
+//   - j particles of the slice go through LDS in tiles of kTileJ, loaded
+//     with coalesced SoA reads and prefetched into registers one tile ahead;
+//   - the LJ lanes of one i are reduced with a fixed xor butterfly, and each
+//     slice writes its partial sum to part[slice][component][position];
+//     the corrector sums slices in ascending order.
+template <bool kMaskSelf>
+__global__ __launch_bounds__(kBlock) void k_force(const Sched* __restrict__ sc, int n, double eps2,
+                                                  const double* __restrict__ px,
+                                                  const double* __restrict__ py,
+                                                  const double* __restrict__ pz,
+                                                  const double* __restrict__ pvx,
+                                                  const double* __restrict__ pvy,
+                                                  const double* __restrict__ pvz,
+                                                  const double* __restrict__ pm,
+                                                  const int* __restrict__ active,
+                                                  double* __restrict__ part) {
+  if (sc->done) return;
+  const int n_act = sc->n_act;
+  if (n_act <= 0) return;
+  const Plan p = make_plan(n_act, n);
+  if ((int)blockIdx.x >= p.items) return;
+
+  __shared__ double sj[7][kTileJ];
+  const int tid = threadIdx.x;
+  const int LJ = 1 << p.lj;
+  const int jsub = tid & (LJ - 1);
+  const int ilane = tid >> p.lj;
+  const int ilanes = kBlock >> p.lj;
+
+  for (int item = blockIdx.x; item < p.items; item += gridDim.x) {
+    const int itile = item / p.s;
+    const int slice = item - itile * p.s;
+    const int j0 = slice * p.len;
+    const int j1 = min(n, j0 + p.len);
+
+    int pos[kIPerLane], gi[kIPerLane];
+    double xi[kIPerLane], yi[kIPerLane], zi[kIPerLane];
+    double vxi[kIPerLane], vyi[kIPerLane], vzi[kIPerLane];
+    Acc6 A[kIPerLane];
+#pragma unroll
+    for (int q = 0; q < kIPerLane; ++q) {
+      pos[q] = itile * p.it + ilane + q * ilanes;
+      const int i = active[min(pos[q], n_act - 1)];
+      gi[q] = i;
+      xi[q] = px[i];
+      yi[q] = py[i];
+      zi[q] = pz[i];
+      vxi[q] = pvx[i];
+      vyi[q] = pvy[i];
+      vzi[q] = pvz[i];
+      A[q] = Acc6{0, 0, 0, 0, 0, 0};
+    }
+
+    // Prefetch of the first tile.
+    double rx = 0, ry = 0, rz = 0, rvx = 0, rvy = 0, rvz = 0, rm = 0;
+    if (j0 < j1 && tid < min(kTileJ, j1 - j0)) {
+      const int j = j0 + tid;
+      rx = px[j]; ry = py[j]; rz = pz[j];
+      rvx = pvx[j]; rvy = pvy[j]; rvz = pvz[j];
+      rm = pm[j];
+    }
+    for (int jt = j0; jt < j1; jt += kTileJ) {
+      const int cnt = min(kTileJ, j1 - jt);
+      __syncthreads();
+      if (tid < cnt) {
+        sj[0][tid] = rx; sj[1][tid] = ry; sj[2][tid] = rz;
+        sj[3][tid] = rvx; sj[4][tid] = rvy; sj[5][tid] = rvz;
+        sj[6][tid] = rm;
+      }
+      __syncthreads();
+      const int nxt = jt + kTileJ;
+      if (nxt < j1 && tid < min(kTileJ, j1 - nxt)) {
+        const int j = nxt + tid;
+        rx = px[j]; ry = py[j]; rz = pz[j];
+        rvx = pvx[j]; rvy = pvy[j]; rvz = pvz[j];
+        rm = pm[j];
+      }
+      for (int k = jsub; k < cnt; k += LJ) {
+        const double xj = sj[0][k], yj = sj[1][k], zj = sj[2][k];
+        const double vxj = sj[3][k], vyj = sj[4][k], vzj = sj[5][k];
+        const double mj = sj[6][k];
+#pragma unroll
+        for (int q = 0; q < kIPerLane; ++q) {
+          if (kMaskSelf) {
+            // eps = 0: the j = i term (r = 0) is excluded explicitly.
+            const bool self = (jt + k) == gi[q];
+            pair_fp64(xi[q], yi[q], zi[q], vxi[q], vyi[q], vzi[q], self ? xi[q] + 1.0 : xj, yj,
+                      zj, vxj, vyj, vzj, self ? 0.0 : mj, eps2, A[q]);
+          } else {
+            // eps > 0: the j = i term is exactly zero (r = w = 0, finite q).
+            pair_fp64(xi[q], yi[q], zi[q], vxi[q], vyi[q], vzi[q], xj, yj, zj, vxj, vyj, vzj, mj,
+                      eps2, A[q]);
+          }
+        }
+      }
+    }
+
+    // Butterfly over the LJ lanes that share an i (consecutive lanes).
+    for (int off = LJ >> 1; off > 0; off >>= 1) {
+#pragma unroll
+      for (int q = 0; q < kIPerLane; ++q) {
+        A[q].ax += shfl_xor_d(A[q].ax, off);
+        A[q].ay += shfl_xor_d(A[q].ay, off);
+        A[q].az += shfl_xor_d(A[q].az, off);
+        A[q].jx += shfl_xor_d(A[q].jx, off);
+        A[q].jy += shfl_xor_d(A[q].jy, off);
+        A[q].jz += shfl_xor_d(A[q].jz, off);
+      }
+    }
+    if (jsub == 0) {
+#pragma unroll
+      for (int q = 0; q < kIPerLane; ++q) {
+        if (pos[q] < n_act) {
+          double* o = part + (size_t)slice * 6 * n_act + pos[q];
+          o[0 * (size_t)n_act] = A[q].ax;
+          o[1 * (size_t)n_act] = A[q].ay;
+          o[2 * (size_t)n_act] = A[q].az;
+          o[3 * (size_t)n_act] = A[q].jx;
+          o[4 * (size_t)n_act] = A[q].jy;
+          o[5 * (size_t)n_act] = A[q].jz;
+        }
+      }
+    }
+  }
+}
+
+// Sum of the slice partials of active position k, slices in ascending order.
+__device__ __forceinline__ void sum_partials(const double* __restrict__ part, int s, int n_act,
+                                             int k, double f[6]) {
+#pragma unroll
+  for (int c = 0; c < 6; ++c) f[c] = part[(size_t)c * n_act + k];
+  for (int sl = 1; sl < s; ++sl) {
+    const double* o = part + (size_t)sl * 6 * n_act + k;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) f[c] += o[(size_t)c * n_act];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Block time steps
+// ---------------------------------------------------------------------------
+
+// Smallest k >= 0 with dt_max / 2^k <= dtstar; kmax + 1 when even dt_min is
+// too large (the caller clamps and counts); 0 when dtstar is not a number
+// below dt_max (including +inf and NaN). With dtstar / dt_max = f 2^e,
+// f in [0.5, 1), the answer is exactly 1 - e.
+__device__ __forceinline__ int level_for(double dtstar, double dt_max, int kmax) {
+  if (!(dtstar < dt_max)) return 0;
+  if (!(dtstar > 0.0)) return kmax + 1;
+  int e;
+  (void)frexp(dtstar / dt_max, &e);
+  return min(1 - e, kmax + 1);
+}
+
+__device__ __forceinline__ double norm3(double a, double b, double c) {
+  return sqrt(a * a + b * b + c * c);
+}
+
+// ---------------------------------------------------------------------------
+// Predictor with the active-set search (Sec. 2.4 steps 5 and 7(a))
+// ---------------------------------------------------------------------------
+//
+// Every workgroup first derives the step from the level histogram: all
+// particles at level k sit on multiples of their step 2^(kmax-k) ticks, so
+// the earliest next time is the next multiple of the smallest step present,
+// and the active set is every particle whose step divides that time, i.e.
+// level >= kmax - ctz(t_next). No O(N) search is needed for the time, and the
+// block size is the histogram's tail sum.
+//
+// Then each lane predicts one particle to t_next (Taylor series through the
+// jerk, Delta = t_next - t_j) into the j stream, and active particles are
+// appended to the active list (wave ballot + one atomic per workgroup; the
+// list order is not deterministic, but no result depends on it).
+__global__ __launch_bounds__(kBlock) void k_predict(Sched* __restrict__ sc, int n, int kmax,
+                                                    double dt_min, int mode, double t_explicit,
+                                                    const double* __restrict__ x,
+                                                    const double* __restrict__ y,
+                                                    const double* __restrict__ z,
+                                                    const double* __restrict__ vx,
+                                                    const double* __restrict__ vy,
+                                                    const double* __restrict__ vz,
+                                                    const double* __restrict__ ax,
+                                                    const double* __restrict__ ay,
+                                                    const double* __restrict__ az,
+                                                    const double* __restrict__ jx,
+                                                    const double* __restrict__ jy,
+                                                    const double* __restrict__ jz,
+                                                    const long long* __restrict__ tick,
+                                                    const int* __restrict__ lev,
+                                                    double* __restrict__ px, double* __restrict__ py,
+                                                    double* __restrict__ pz,
+                                                    double* __restrict__ pvx,
+                                                    double* __restrict__ pvy,
+                                                    double* __restrict__ pvz,
+                                                    int* __restrict__ active) {
+  __shared__ long long s_tnext;
+  __shared__ int s_kthr, s_done, s_base;
+  __shared__ int s_wcount[kBlock / 64];
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    long long t_next;
+    int kthr, nact = 0, done = 0;
+    if (mode == kPredAuto) {
+      int kmx = 0;
+      for (int k = kmax; k >= 0; --k)
+        if (sc->hist[k] > 0) { kmx = k; break; }
+      const long long step = 1LL << (kmax - kmx);
+      t_next = (sc->t_now / step + 1) * step;
+      const int tz = __builtin_ctzll((unsigned long long)t_next);
+      kthr = max(0, kmax - tz);
+      for (int k = kthr; k <= kmax; ++k) nact += sc->hist[k];
+      done = t_next > sc->t_end;
+    } else if (mode == kPredAll) {
+      t_next = sc->t_now;
+      kthr = 0;
+      nact = n;
+    } else {
+      t_next = sc->t_now;
+      kthr = kmax + 1;  // nobody active
+    }
+    s_tnext = t_next;
+    s_kthr = kthr;
+    s_done = done;
+    if (blockIdx.x == 0) {
+      sc->t_next = t_next;
+      sc->kthr = kthr;
+      sc->n_act = nact;
+      sc->done = done;
+    }
+  }
+  __syncthreads();
+  if (s_done) return;
+
+  const int j = blockIdx.x * kBlock + tid;
+  bool act = false;
+  if (j < n) {
+    const double dt = (mode == kPredExplicit) ? t_explicit - (double)tick[j] * dt_min
+                                              : (double)(s_tnext - tick[j]) * dt_min;
+    const double a_x = ax[j], a_y = ay[j], a_z = az[j];
+    const double j_x = jx[j], j_y = jy[j], j_z = jz[j];
+    const double v_x = vx[j], v_y = vy[j], v_z = vz[j];
+    const double h2 = 0.5 * dt, h3 = dt * (1.0 / 3.0);
+    // x + dt (v + dt/2 (a + dt/3 jerk)),  v + dt (a + dt/2 jerk)
+    px[j] = fma(dt, fma(h2, fma(h3, j_x, a_x), v_x), x[j]);
+    py[j] = fma(dt, fma(h2, fma(h3, j_y, a_y), v_y), y[j]);
+    pz[j] = fma(dt, fma(h2, fma(h3, j_z, a_z), v_z), z[j]);
+    pvx[j] = fma(dt, fma(h2, j_x, a_x), v_x);
+    pvy[j] = fma(dt, fma(h2, j_y, a_y), v_y);
+    pvz[j] = fma(dt, fma(h2, j_z, a_z), v_z);
+    act = lev[j] >= s_kthr;
+  }
+  // Workgroup compaction of the active flags.
+  const unsigned long long ball = __ballot(act);
+  const int wave = tid >> 6, lane = tid & 63;
+  const int before = __popcll(ball & ((1ULL << lane) - 1ULL));
+  if (lane == 0) s_wcount[wave] = __popcll(ball);
+  __syncthreads();
+  if (tid == 0) {
+    int tot = 0;
+    for (int w = 0; w < kBlock / 64; ++w) {
+      const int c = s_wcount[w];
+      s_wcount[w] = tot;
+      tot += c;
+    }
+    s_base = tot ? atomicAdd(&sc->cnt, tot) : 0;
+  }
+  __syncthreads();
+  if (act) active[s_base + s_wcount[wave] + before] = j;
+}
+
+// ---------------------------------------------------------------------------
+// Corrector and new block step (Sec. 2.4 step 7(d); Sec. 3.2)
+// ---------------------------------------------------------------------------
+//
+// Per active particle: sum the slice partials of the new force (a1, j1);
+// Hermite interpolation of (a0, j0, a1, j1) over h gives the 2nd and 3rd
+// derivatives a2, a3 at the start of the step; corrected
+//   x = x_p + a2 h^4/24 + a3 h^5/120,  v = v_p + a2 h^3/6 + a3 h^4/24;
+// new step from the Aarseth criterion with the derivatives carried to the end
+// of the step, quantised to a power of two (shrink freely, grow by one level
+// only where the doubled step divides the new time, clamp at dt_min).
+__global__ __launch_bounds__(kBlock) void k_correct(Sched* __restrict__ sc, int n, int kmax,
+                                                    double dt_min, double dt_max, double eta,
+                                                    double* __restrict__ x, double* __restrict__ y,
+                                                    double* __restrict__ z,
+                                                    double* __restrict__ vx,
+                                                    double* __restrict__ vy,
+                                                    double* __restrict__ vz,
+                                                    double* __restrict__ ax,
+                                                    double* __restrict__ ay,
+                                                    double* __restrict__ az,
+                                                    double* __restrict__ jx,
+                                                    double* __restrict__ jy,
+                                                    double* __restrict__ jz,
+                                                    long long* __restrict__ tick,
+                                                    int* __restrict__ lev,
+                                                    const double* __restrict__ px,
+                                                    const double* __restrict__ py,
+                                                    const double* __restrict__ pz,
+                                                    const double* __restrict__ pvx,
+                                                    const double* __restrict__ pvy,
+                                                    const double* __restrict__ pvz,
+                                                    const int* __restrict__ active,
+                                                    const double* __restrict__ part) {
+  if (sc->done) return;
+  const int n_act = sc->n_act;
+  const long long t_next = sc->t_next;
+  const Plan p = make_plan(n_act, n);
+  __shared__ int lhist[kMaxLevels + 1];
+  __shared__ int lclamp, lbad;
+  const int tid = threadIdx.x;
+  if (tid <= kMaxLevels) lhist[tid] = 0;
+  if (tid == 0) { lclamp = 0; lbad = 0; }
+  __syncthreads();
+
+  for (int k = blockIdx.x * kBlock + tid; k < n_act; k += gridDim.x * kBlock) {
+    const int i = active[k];
+    double f[6];
+    sum_partials(part, p.s, n_act, k, f);
+    bool finite = true;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) finite = finite && isfinite(f[c]);
+    if (!finite) lbad = 1;
+
+    const int lv = lev[i];
+    const double h = (double)(1LL << (kmax - lv)) * dt_min;
+    const double h2 = h * h, h3 = h2 * h;
+    const double a0[3] = {ax[i], ay[i], az[i]};
+    const double j0[3] = {jx[i], jy[i], jz[i]};
+    const double xp[3] = {px[i], py[i], pz[i]};
+    const double vp[3] = {pvx[i], pvy[i], pvz[i]};
+    double a2[3], a3[3], a2e[3], xn[3], vn[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double da = a0[d] - f[d];
+      a2[d] = (-6.0 * da - h * (4.0 * j0[d] + 2.0 * f[3 + d])) / h2;
+      a3[d] = (12.0 * da + 6.0 * h * (j0[d] + f[3 + d])) / h3;
+      xn[d] = xp[d] + a2[d] * (h2 * h2) / 24.0 + a3[d] * (h2 * h3) / 120.0;
+      vn[d] = vp[d] + a2[d] * h3 / 6.0 + a3[d] * (h2 * h2) / 24.0;
+      a2e[d] = a2[d] + h * a3[d];
+    }
+    const double na1 = norm3(f[0], f[1], f[2]);
+    const double nj1 = norm3(f[3], f[4], f[5]);
+    const double na2 = norm3(a2e[0], a2e[1], a2e[2]);
+    const double na3 = norm3(a3[0], a3[1], a3[2]);
+    const double dtstar = sqrt(eta * (na1 * na2 + nj1 * nj1) / (nj1 * na3 + na2 * na2));
+
+    const int kc = level_for(dtstar, dt_max, kmax);
+    int nl;
+    if (kc >= lv) {
+      nl = kc;
+    } else if (lv >= 1 && (t_next & ((1LL << (kmax - lv + 1)) - 1)) == 0) {
+      nl = lv - 1;
+    } else {
+      nl = lv;
+    }
+    if (nl > kmax) {
+      nl = kmax;
+      atomicAdd(&lclamp, 1);
+    }
+    x[i] = xn[0]; y[i] = xn[1]; z[i] = xn[2];
+    vx[i] = vn[0]; vy[i] = vn[1]; vz[i] = vn[2];
+    ax[i] = f[0]; ay[i] = f[1]; az[i] = f[2];
+    jx[i] = f[3]; jy[i] = f[4]; jz[i] = f[5];
+    tick[i] = t_next;
+    lev[i] = nl;
+    if (nl != lv) {
+      atomicAdd(&lhist[lv], -1);
+      atomicAdd(&lhist[nl], 1);
+    }
+  }
+  __syncthreads();
+  if (tid <= kmax && lhist[tid] != 0) atomicAdd(&sc->hist[tid], lhist[tid]);
+  if (tid == 0) {
+    if (lclamp) atomicAdd((unsigned long long*)&sc->clamps, (unsigned long long)lclamp);
+    if (lbad) atomicOr(&sc->nonfinite, 1);
+    if (blockIdx.x == 0) {
+      sc->block_steps += 1;
+      sc->particle_steps += n_act;
+      sc->pairs += (long long)n_act * n;
+      sc->t_now = t_next;
+      sc->cnt = 0;
+    }
+  }
+}
+
+// Initial block steps (Sec. 2.4 step 3; Sec. 3.2: the same eta from the
+// initial calculation on): dt* = eta |a| / |jerk|, quantised to the largest
+// dt_max / 2^k <= dt*, clamped at dt_min. Also stores a, jerk, t_i = t_now
+// and the level histogram (zeroed beforehand).
+__global__ __launch_bounds__(kBlock) void k_init_dt(Sched* __restrict__ sc, int n, int kmax,
+                                                    double dt_max, double eta,
+                                                    double* __restrict__ ax,
+                                                    double* __restrict__ ay,
+                                                    double* __restrict__ az,
+                                                    double* __restrict__ jx,
+                                                    double* __restrict__ jy,
+                                                    double* __restrict__ jz,
+                                                    long long* __restrict__ tick,
+                                                    int* __restrict__ lev,
+                                                    const int* __restrict__ active,
+                                                    const double* __restrict__ part) {
+  const int n_act = sc->n_act;
+  const Plan p = make_plan(n_act, n);
+  __shared__ int lhist[kMaxLevels + 1];
+  __shared__ int lclamp, lbad;
+  const int tid = threadIdx.x;
+  if (tid <= kMaxLevels) lhist[tid] = 0;
+  if (tid == 0) { lclamp = 0; lbad = 0; }
+  __syncthreads();
+  for (int k = blockIdx.x * kBlock + tid; k < n_act; k += gridDim.x * kBlock) {
+    const int i = active[k];
+    double f[6];
+    sum_partials(part, p.s, n_act, k, f);
+    bool finite = true;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) finite = finite && isfinite(f[c]);
+    if (!finite) lbad = 1;
+    const double dtstar = eta * norm3(f[0], f[1], f[2]) / norm3(f[3], f[4], f[5]);
+    int nl = level_for(dtstar, dt_max, kmax);
+    if (nl > kmax) {
+      nl = kmax;
+      atomicAdd(&lclamp, 1);
+    }
+    ax[i] = f[0]; ay[i] = f[1]; az[i] = f[2];
+    jx[i] = f[3]; jy[i] = f[4]; jz[i] = f[5];
+    tick[i] = sc->t_now;
+    lev[i] = nl;
+    atomicAdd(&lhist[nl], 1);
+  }
+  __syncthreads();
+  if (tid <= kmax && lhist[tid] != 0) atomicAdd(&sc->hist[tid], lhist[tid]);
+  if (tid == 0) {
+    if (lclamp) atomicAdd((unsigned long long*)&sc->clamps, (unsigned long long)lclamp);
+    if (lbad) atomicOr(&sc->nonfinite, 1);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Energy (Eq. (2), softened and unsoftened potentials)
+// ---------------------------------------------------------------------------
+//
+// Items are (i tile of 256, j slice); each lane sums phi_i over its slice
+// with the j = i term excluded, then the workgroup reduces -m_i phi_i / 2
+// (and the kinetic term, on slice 0) in a fixed tree. A second kernel sums
+// the item partials in a fixed order.
+__global__ __launch_bounds__(kBlock) void k_energy(int n, double eps2, int unsoft,
+                                                   const double* __restrict__ x,
+                                                   const double* __restrict__ y,
+                                                   const double* __restrict__ z,
+                                                   const double* __restrict__ vx,
+                                                   const double* __restrict__ vy,
+                                                   const double* __restrict__ vz,
+                                                   const double* __restrict__ m,
+                                                   double* __restrict__ ebuf) {
+  const EPlan e = make_eplan(n);
+  __shared__ double sj[4][kTileJ];
+  __shared__ double red[3][kBlock];
+  const int tid = threadIdx.x;
+  for (int item = blockIdx.x; item < e.items; item += gridDim.x) {
+    const int itile = item / e.s, slice = item - itile * e.s;
+    const int i = itile * kBlock + tid;
+    const int j0 = slice * e.len, j1 = min(n, j0 + e.len);
+    const int ii = min(i, n - 1);
+    const double xi = x[ii], yi = y[ii], zi = z[ii];
+    double phi = 0.0, phiu = 0.0;
+    for (int jt = j0; jt < j1; jt += kTileJ) {
+      const int cnt = min(kTileJ, j1 - jt);
+      __syncthreads();
+      if (tid < cnt) {
+        sj[0][tid] = x[jt + tid];
+        sj[1][tid] = y[jt + tid];
+        sj[2][tid] = z[jt + tid];
+        sj[3][tid] = m[jt + tid];
+      }
+      __syncthreads();
+      for (int k = 0; k < cnt; ++k) {
+        const double dx = sj[0][k] - xi, dy = sj[1][k] - yi, dz = sj[2][k] - zi;
+        const bool self = (jt + k) == ii;
+        const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+        const double mj = self ? 0.0 : sj[3][k];
+        phi = fma(mj, rsqrt_fp64(self ? 1.0 : r2 + eps2), phi);
+        if (unsoft) phiu = fma(mj, rsqrt_fp64(self ? 1.0 : r2), phiu);
+      }
+    }
+    double kin = 0.0, pot = 0.0, potu = 0.0;
+    if (i < n) {
+      const double mi = m[i];
+      pot = -0.5 * mi * phi;
+      potu = -0.5 * mi * phiu;
+      if (slice == 0) kin = 0.5 * mi * fma(vz[i], vz[i], fma(vy[i], vy[i], vx[i] * vx[i]));
+    }
+    red[0][tid] = kin;
+    red[1][tid] = pot;
+    red[2][tid] = potu;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+      if (tid < w) {
+        red[0][tid] += red[0][tid + w];
+        red[1][tid] += red[1][tid + w];
+        red[2][tid] += red[2][tid + w];
+      }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      ebuf[3 * item + 0] = red[0][0];
+      ebuf[3 * item + 1] = red[1][0];
+      ebuf[3 * item + 2] = red[2][0];
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_energy_final(int n, double* __restrict__ ebuf,
+                                                         double* __restrict__ out) {
+  const EPlan e = make_eplan(n);
+  __shared__ double red[3][kBlock];
+  const int tid = threadIdx.x;
+  double s0 = 0, s1 = 0, s2 = 0;
+  for (int it = tid; it < e.items; it += kBlock) {
+    s0 += ebuf[3 * it + 0];
+    s1 += ebuf[3 * it + 1];
+    s2 += ebuf[3 * it + 2];
+  }
+  red[0][tid] = s0;
+  red[1][tid] = s1;
+  red[2][tid] = s2;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (tid < w) {
+      red[0][tid] += red[0][tid + w];
+      red[1][tid] += red[1][tid + w];
+      red[2][tid] += red[2][tid + w];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    out[0] = red[0][0];
+    out[1] = red[1][0];
+    out[2] = red[2][0];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// State movement and small bookkeeping kernels
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ bool fin3(double a, double b, double c) {
+  return isfinite(a) && isfinite(b) && isfinite(c);
+}
+
+// Row-major (n, 3) inputs to SoA; masses copied; validation of the inputs.
+__global__ void k_load(Sched* __restrict__ sc, int n, const double* __restrict__ m_in,
+                       const double* __restrict__ x_in, const double* __restrict__ v_in,
+                       double* __restrict__ m, double* __restrict__ x, double* __restrict__ y,
+                       double* __restrict__ z, double* __restrict__ vx, double* __restrict__ vy,
+                       double* __restrict__ vz, double* __restrict__ ax, double* __restrict__ ay,
+                       double* __restrict__ az, double* __restrict__ jx, double* __restrict__ jy,
+                       double* __restrict__ jz, long long* __restrict__ tick,
+                       int* __restrict__ lev) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double mi = m_in[i];
+  const double x0 = x_in[3 * i], x1 = x_in[3 * i + 1], x2 = x_in[3 * i + 2];
+  const double v0 = v_in[3 * i], v1 = v_in[3 * i + 1], v2 = v_in[3 * i + 2];
+  if (!(isfinite(mi) && mi >= 0.0 && fin3(x0, x1, x2) && fin3(v0, v1, v2))) atomicOr(&sc->bad_input, 1);
+  m[i] = mi;
+  x[i] = x0; y[i] = x1; z[i] = x2;
+  vx[i] = v0; vy[i] = v1; vz[i] = v2;
+  ax[i] = 0; ay[i] = 0; az[i] = 0;
+  jx[i] = 0; jy[i] = 0; jz[i] = 0;
+  tick[i] = 0;
+  lev[i] = 0;
+}
+
+__global__ void k_reset_sched(Sched* __restrict__ sc, long long t_now) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    sc->t_now = t_now;
+    sc->t_next = 0;
+    sc->t_end = 0;
+    sc->n_act = 0;
+    sc->kthr = 0;
+    sc->done = 0;
+    sc->cnt = 0;
+    sc->nonfinite = 0;
+    sc->bad_input = 0;
+    sc->block_steps = 0;
+    sc->particle_steps = 0;
+    sc->pairs = 0;
+    sc->clamps = 0;
+  }
+  if (blockIdx.x == 0 && threadIdx.x <= kMaxLevels) sc->hist[threadIdx.x] = 0;
+}
+
+// Prepares a sequence of automatic steps: sets the stop time and clears the
+// compaction counter.
+__global__ void k_set_tend(Sched* __restrict__ sc, long long t_end) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    sc->t_end = t_end;
+    sc->cnt = 0;
+    sc->done = 0;
+  }
+}
+
+// Explicit active list for gd_force(idx, ...): range-checked copy.
+__global__ void k_set_active(Sched* __restrict__ sc, int n, const int32_t* __restrict__ idx,
+                             int n_act, int* __restrict__ active) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k == 0) {
+    sc->n_act = n_act;
+    sc->done = 0;
+  }
+  if (k >= n_act) return;
+  int i = idx[k];
+  if (i < 0 || i >= n) {
+    atomicOr(&sc->bad_input, 1);
+    i = 0;
+  }
+  active[k] = i;
+}
+
+// Forces of the current active list as (n_act, 3) row-major arrays.
+__global__ void k_gather_forces(const Sched* __restrict__ sc, int n, const double* __restrict__ part,
+                                double* __restrict__ acc, double* __restrict__ jerk) {
+  const int n_act = sc->n_act;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_act) return;
+  const Plan p = make_plan(n_act, n);
+  double f[6];
+  sum_partials(part, p.s, n_act, k, f);
+  if (acc) {
+    acc[3 * k] = f[0]; acc[3 * k + 1] = f[1]; acc[3 * k + 2] = f[2];
+  }
+  if (jerk) {
+    jerk[3 * k] = f[3]; jerk[3 * k + 1] = f[4]; jerk[3 * k + 2] = f[5];
+  }
+}
+
+__global__ void k_copy_active(const Sched* __restrict__ sc, const int* __restrict__ active,
+                              int32_t* __restrict__ out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < sc->n_act) out[k] = active[k];
+}
+
+__global__ void k_get_state(int n, int kmax, double dt_min, const double* __restrict__ x,
+                            const double* __restrict__ y, const double* __restrict__ z,
+                            const double* __restrict__ vx, const double* __restrict__ vy,
+                            const double* __restrict__ vz, const double* __restrict__ ax,
+                            const double* __restrict__ ay, const double* __restrict__ az,
+                            const double* __restrict__ jx, const double* __restrict__ jy,
+                            const double* __restrict__ jz, const long long* __restrict__ tick,
+                            const int* __restrict__ lev, double* __restrict__ xo,
+                            double* __restrict__ vo, double* __restrict__ ao,
+                            double* __restrict__ jo, double* __restrict__ to,
+                            double* __restrict__ dto) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (xo) { xo[3 * i] = x[i]; xo[3 * i + 1] = y[i]; xo[3 * i + 2] = z[i]; }
+  if (vo) { vo[3 * i] = vx[i]; vo[3 * i + 1] = vy[i]; vo[3 * i + 2] = vz[i]; }
+  if (ao) { ao[3 * i] = ax[i]; ao[3 * i + 1] = ay[i]; ao[3 * i + 2] = az[i]; }
+  if (jo) { jo[3 * i] = jx[i]; jo[3 * i + 1] = jy[i]; jo[3 * i + 2] = jz[i]; }
+  if (to) to[i] = (double)tick[i] * dt_min;
+  if (dto) dto[i] = (double)(1LL << (kmax - lev[i])) * dt_min;
+}
+
+// Inverse of k_get_state with validation: dt_i must be dt_min * 2^k for
+// k in [0, kmax], t_i an exact multiple of dt_i, t_i <= t_now < t_i + dt_i.
+__global__ void k_set_state(Sched* __restrict__ sc, int n, int kmax, double dt_min,
+                            long long t_now, const double* __restrict__ xi,
+                            const double* __restrict__ vi, const double* __restrict__ ai,
+                            const double* __restrict__ ji, const double* __restrict__ ti,
+                            const double* __restrict__ dti, double* __restrict__ x,
+                            double* __restrict__ y, double* __restrict__ z,
+                            double* __restrict__ vx, double* __restrict__ vy,
+                            double* __restrict__ vz, double* __restrict__ ax,
+                            double* __restrict__ ay, double* __restrict__ az,
+                            double* __restrict__ jx, double* __restrict__ jy,
+                            double* __restrict__ jz, long long* __restrict__ tick,
+                            int* __restrict__ lev) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  bool ok = fin3(xi[3 * i], xi[3 * i + 1], xi[3 * i + 2]) &&
+            fin3(vi[3 * i], vi[3 * i + 1], vi[3 * i + 2]) &&
+            fin3(ai[3 * i], ai[3 * i + 1], ai[3 * i + 2]) &&
+            fin3(ji[3 * i], ji[3 * i + 1], ji[3 * i + 2]);
+  const double steps = dti[i] / dt_min;  // exact for powers of two
+  int e = 0;
+  const double f = frexp(steps, &e);
+  const int lg = e - 1;  // steps = 2^lg when f == 0.5
+  ok = ok && f == 0.5 && lg >= 0 && lg <= kmax;
+  const int lv = kmax - (ok ? lg : 0);
+  const double tt = ti[i] / dt_min;
+  ok = ok && isfinite(tt) && tt >= 0.0 && tt < 9.0e15 && tt == floor(tt);
+  const long long tk = ok ? (long long)tt : 0;
+  const long long st = 1LL << (kmax - lv);
+  ok = ok && (tk % st) == 0 && tk <= t_now && t_now < tk + st;
+  if (!ok) atomicOr(&sc->bad_input, 1);
+  x[i] = xi[3 * i]; y[i] = xi[3 * i + 1]; z[i] = xi[3 * i + 2];
+  vx[i] = vi[3 * i]; vy[i] = vi[3 * i + 1]; vz[i] = vi[3 * i + 2];
+  ax[i] = ai[3 * i]; ay[i] = ai[3 * i + 1]; az[i] = ai[3 * i + 2];
+  jx[i] = ji[3 * i]; jy[i] = ji[3 * i + 1]; jz[i] = ji[3 * i + 2];
+  tick[i] = tk;
+  lev[i] = lv;
+  atomicAdd(&sc->hist[lv], 1);
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+
+static inline int grid_for(int n) { return (n + kBlock - 1) / kBlock; }
+
+hipError_t launch_load(const Dev& d, const Consts& c, const double* m, const double* x,
+                       const double* v, hipStream_t s) {
+  hipLaunchKernelGGL(k_load, dim3(grid_for(c.n)), dim3(kBlock), 0, s, d.sc, c.n, m, x, v, d.m,
+                     d.x, d.y, d.z, d.vx, d.vy, d.vz, d.ax, d.ay, d.az, d.jx, d.jy, d.jz, d.tick,
+                     d.lev);
+  return hipGetLastError();
+}
+
+hipError_t launch_predict(const Dev& d, const Consts& c, int mode, double t_explicit,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_predict, dim3(grid_for(c.n)), dim3(kBlock), 0, s, d.sc, c.n, c.kmax,
+                     c.dt_min, mode, t_explicit, d.x, d.y, d.z, d.vx, d.vy, d.vz, d.ax, d.ay,
+                     d.az, d.jx, d.jy, d.jz, d.tick, d.lev, d.px, d.py, d.pz, d.pvx, d.pvy,
+                     d.pvz, d.active);
+  return hipGetLastError();
+}
+
+hipError_t launch_force(const Dev& d, const Consts& c, hipStream_t s) {
+  if (c.eps2 > 0.0) {
+    hipLaunchKernelGGL(k_force<false>, dim3(kForceGrid), dim3(kBlock), 0, s, d.sc, c.n, c.eps2,
+                       d.px, d.py, d.pz, d.pvx, d.pvy, d.pvz, d.m, d.active, d.part);
+  } else {
+    hipLaunchKernelGGL(k_force<true>, dim3(kForceGrid), dim3(kBlock), 0, s, d.sc, c.n, c.eps2,
+                       d.px, d.py, d.pz, d.pvx, d.pvy, d.pvz, d.m, d.active, d.part);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_correct(const Dev& d, const Consts& c, hipStream_t s) {
+  hipLaunchKernelGGL(k_correct, dim3(grid_for(c.n)), dim3(kBlock), 0, s, d.sc, c.n, c.kmax,
+                     c.dt_min, c.dt_max, c.eta, d.x, d.y, d.z, d.vx, d.vy, d.vz, d.ax, d.ay,
+                     d.az, d.jx, d.jy, d.jz, d.tick, d.lev, d.px, d.py, d.pz, d.pvx, d.pvy,
+                     d.pvz, d.active, d.part);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_dt(const Dev& d, const Consts& c, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_dt, dim3(grid_for(c.n)), dim3(kBlock), 0, s, d.sc, c.n, c.kmax,
+                     c.dt_max, c.eta, d.ax, d.ay, d.az, d.jx, d.jy, d.jz, d.tick, d.lev,
+                     d.active, d.part);
+  return hipGetLastError();
+}
+
+hipError_t launch_energy(const Dev& d, const Consts& c, int unsoft, hipStream_t s) {
+  hipLaunchKernelGGL(k_energy, dim3(kEnergyGrid), dim3(kBlock), 0, s, c.n, c.eps2, unsoft, d.x,
+                     d.y, d.z, d.vx, d.vy, d.vz, d.m, d.ebuf);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const EPlan ep = make_eplan(c.n);
+  hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kBlock), 0, s, c.n, d.ebuf,
+                     d.ebuf + 3 * (size_t)ep.items);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_tend(const Dev& d, long long t_end, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_tend, dim3(1), dim3(64), 0, s, d.sc, t_end);
+  return hipGetLastError();
+}
+
+hipError_t launch_reset_sched(const Dev& d, long long t_now, hipStream_t s) {
+  hipLaunchKernelGGL(k_reset_sched, dim3(1), dim3(64), 0, s, d.sc, t_now);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_active(const Dev& d, const Consts& c, const int32_t* idx, int n_act,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_set_active, dim3(grid_for(n_act > 0 ? n_act : 1)), dim3(kBlock), 0, s,
+                     d.sc, c.n, idx, n_act, d.active);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_forces(const Dev& d, const Consts& c, int n_rows_max, double* acc,
+                                double* jerk, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_forces, dim3(grid_for(n_rows_max)), dim3(kBlock), 0, s, d.sc, c.n,
+                     d.part, acc, jerk);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_active(const Dev& d, const Consts& c, int32_t* idx, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_active, dim3(grid_for(c.n)), dim3(kBlock), 0, s, d.sc, d.active, idx);
+  return hipGetLastError();
+}
+
+hipError_t launch_get_state(const Dev& d, const Consts& c, double* x, double* v, double* a,
+                            double* jerk, double* t_i, double* dt_i, hipStream_t s) {
+  hipLaunchKernelGGL(k_get_state, dim3(grid_for(c.n)), dim3(kBlock), 0, s, c.n, c.kmax, c.dt_min,
+                     d.x, d.y, d.z, d.vx, d.vy, d.vz, d.ax, d.ay, d.az, d.jx, d.jy, d.jz, d.tick,
+                     d.lev, x, v, a, jerk, t_i, dt_i);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_state(const Dev& d, const Consts& c, const double* x, const double* v,
+                            const double* a, const double* jerk, const double* t_i,
+                            const double* dt_i, long long t_now, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_state, dim3(grid_for(c.n)), dim3(kBlock), 0, s, d.sc, c.n, c.kmax,
+                     c.dt_min, t_now, x, v, a, jerk, t_i, dt_i, d.x, d.y, d.z, d.vx, d.vy, d.vz,
+                     d.ax, d.ay, d.az, d.jx, d.jy, d.jz, d.tick, d.lev);
+  return hipGetLastError();
+}
+
+}  // namespace gd

@@ -1,0 +1,229 @@
+"""Python binding of the C ABI in include/gravidy_hip.h (argument marshalling only).
+
+Every function here has the name of the C entry point it calls; all
+arithmetic runs in the HIP library. PyTorch supplies device memory (the
+workspace and the array arguments, as CUDA/HIP tensors) and the stream.
+
+The library must have been built (paper_1702_00440_amd/build.py, or the
+repository's build entry point); importing it fails loudly otherwise. torch is
+imported first so that the library binds to the HIP runtime torch loaded.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgravidy_hip.so")
+
+GD_OK, GD_EINVAL, GD_ENOMEM, GD_EHIP, GD_ESTATE, GD_ENONFINITE = 0, -1, -2, -3, -4, -5
+_NAMES = {GD_EINVAL: "GD_EINVAL", GD_ENOMEM: "GD_ENOMEM", GD_EHIP: "GD_EHIP",
+          GD_ESTATE: "GD_ESTATE", GD_ENONFINITE: "GD_ENONFINITE"}
+
+
+class GdError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class gd_params(C.Structure):
+    _fields_ = [("eta", C.c_double), ("eps", C.c_double), ("dt_max", C.c_double),
+                ("dt_min", C.c_double), ("flags", C.c_int32)]
+
+
+class gd_stats(C.Structure):
+    _fields_ = [("t", C.c_double), ("block_steps", C.c_int64), ("particle_steps", C.c_int64),
+                ("pair_interactions", C.c_int64), ("dtmin_clamps", C.c_int64),
+                ("e0", C.c_double), ("e", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+_VP = C.c_void_p
+
+
+def library():
+    """The loaded HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"HIP library not built: {LIB_PATH} is missing "
+                          "(run paper_1702_00440_amd/build.py)")
+    lib = C.CDLL(LIB_PATH)
+    i64, st = C.c_int64, C.c_int
+    lib.gd_workspace_bytes.argtypes = [i64, C.POINTER(gd_params), C.POINTER(C.c_size_t)]
+    lib.gd_init.argtypes = [C.POINTER(_VP), C.POINTER(gd_params), i64, _VP, _VP, _VP, _VP, C.c_size_t, _VP]
+    lib.gd_predict.argtypes = [_VP, C.POINTER(C.c_double)]
+    lib.gd_force.argtypes = [_VP, _VP, i64, _VP, _VP]
+    lib.gd_active.argtypes = [_VP, _VP, C.POINTER(i64)]
+    lib.gd_correct.argtypes = [_VP]
+    lib.gd_step_to.argtypes = [_VP, C.c_double, C.POINTER(gd_stats)]
+    lib.gd_energy.argtypes = [_VP, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    lib.gd_get_state.argtypes = [_VP, _VP, _VP, _VP, _VP, _VP, _VP, C.POINTER(C.c_double)]
+    lib.gd_set_state.argtypes = [_VP, _VP, _VP, _VP, _VP, _VP, _VP, C.c_double]
+    lib.gd_stats_get.argtypes = [_VP, C.POINTER(gd_stats)]
+    for name in ["gd_workspace_bytes", "gd_init", "gd_predict", "gd_force", "gd_active", "gd_correct",
+                 "gd_step_to", "gd_energy", "gd_get_state", "gd_set_state", "gd_stats_get"]:
+        getattr(lib, name).restype = st
+    lib.gd_destroy.argtypes = [_VP]
+    lib.gd_destroy.restype = None
+    lib.gd_last_error.argtypes = [_VP]
+    lib.gd_last_error.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, ctx) -> None:
+    if rc != GD_OK:
+        msg = library().gd_last_error(ctx)
+        raise GdError(rc, msg.decode() if msg else "")
+
+
+def _ptr(t, dtype, shape=None, name="array"):
+    """Device pointer of a contiguous tensor of the given dtype (None -> NULL)."""
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t.data_ptr()
+
+
+def _stream_handle(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def make_params(eta=0.01, eps=1e-4, dt_max=0.125, dt_min=2.0 ** -22, flags=0) -> gd_params:
+    return gd_params(float(eta), float(eps), float(dt_max), float(dt_min), int(flags))
+
+
+def gd_workspace_bytes(n: int, params: gd_params | None = None) -> int:
+    out = C.c_size_t()
+    rc = library().gd_workspace_bytes(int(n), C.byref(params) if params is not None else None, C.byref(out))
+    _check(rc, None)
+    return int(out.value)
+
+
+def gd_init(params: gd_params, m, x, v, workspace, stream=None):
+    """Returns the context handle (an opaque pointer)."""
+    n = m.shape[0]
+    ctx = _VP()
+    rc = library().gd_init(C.byref(ctx), C.byref(params), n, _ptr(m, torch.float64, (n,), "m"),
+                           _ptr(x, torch.float64, (n, 3), "x"), _ptr(v, torch.float64, (n, 3), "v"),
+                           _ptr(workspace, torch.uint8, None, "workspace"), workspace.numel(),
+                           _stream_handle(stream))
+    _check(rc, None)
+    return ctx
+
+
+def gd_predict(ctx, t: float | None = None) -> None:
+    tp = C.byref(C.c_double(t)) if t is not None else None
+    _check(library().gd_predict(ctx, tp), ctx)
+
+
+def gd_force(ctx, idx=None, acc=None, jerk=None) -> None:
+    n_act = 0 if idx is None else idx.shape[0]
+    _check(library().gd_force(ctx, _ptr(idx, torch.int32, None, "idx"), n_act,
+                              _ptr(acc, torch.float64, None, "acc"), _ptr(jerk, torch.float64, None, "jerk")), ctx)
+
+
+def gd_active(ctx, idx=None) -> int:
+    n = C.c_int64()
+    _check(library().gd_active(ctx, _ptr(idx, torch.int32, None, "idx"), C.byref(n)), ctx)
+    return int(n.value)
+
+
+def gd_correct(ctx) -> None:
+    _check(library().gd_correct(ctx), ctx)
+
+
+def gd_step_to(ctx, t_end: float) -> dict:
+    st = gd_stats()
+    _check(library().gd_step_to(ctx, float(t_end), C.byref(st)), ctx)
+    return st.as_dict()
+
+
+def gd_energy(ctx, unsoftened: bool = False):
+    ek, ep, eu = C.c_double(), C.c_double(), C.c_double()
+    _check(library().gd_energy(ctx, C.byref(ek), C.byref(ep), C.byref(eu) if unsoftened else None), ctx)
+    return (ek.value, ep.value, eu.value) if unsoftened else (ek.value, ep.value)
+
+
+def gd_get_state(ctx, x=None, v=None, a=None, jerk=None, t_i=None, dt_i=None) -> float:
+    t_now = C.c_double()
+    f = torch.float64
+    _check(library().gd_get_state(ctx, _ptr(x, f, None, "x"), _ptr(v, f, None, "v"), _ptr(a, f, None, "a"),
+                                  _ptr(jerk, f, None, "jerk"), _ptr(t_i, f, None, "t_i"),
+                                  _ptr(dt_i, f, None, "dt_i"), C.byref(t_now)), ctx)
+    return t_now.value
+
+
+def gd_set_state(ctx, x, v, a, jerk, t_i, dt_i, t_now: float) -> None:
+    f = torch.float64
+    _check(library().gd_set_state(ctx, _ptr(x, f, None, "x"), _ptr(v, f, None, "v"), _ptr(a, f, None, "a"),
+                                  _ptr(jerk, f, None, "jerk"), _ptr(t_i, f, None, "t_i"),
+                                  _ptr(dt_i, f, None, "dt_i"), float(t_now)), ctx)
+
+
+def gd_stats_get(ctx) -> dict:
+    st = gd_stats()
+    _check(library().gd_stats_get(ctx, C.byref(st)), ctx)
+    return st.as_dict()
+
+
+def gd_destroy(ctx) -> None:
+    if ctx:
+        library().gd_destroy(ctx)
+
+
+def gd_last_error(ctx=None) -> str:
+    msg = library().gd_last_error(ctx)
+    return msg.decode() if msg else ""
+
+
+class Cluster:
+    """One context plus the device workspace it owns (a torch uint8 tensor)."""
+
+    def __init__(self, m, x, v, eta=0.01, eps=1e-4, dt_max=0.125, dt_min=2.0 ** -22,
+                 device="cuda", stream=None):
+        self.params = make_params(eta, eps, dt_max, dt_min)
+        dev = torch.device(device)
+        self.m = torch.as_tensor(m, dtype=torch.float64).to(dev).contiguous()
+        self.n = self.m.shape[0]
+        xt = torch.as_tensor(x, dtype=torch.float64).to(dev).reshape(self.n, 3).contiguous()
+        vt = torch.as_tensor(v, dtype=torch.float64).to(dev).reshape(self.n, 3).contiguous()
+        nbytes = gd_workspace_bytes(self.n, self.params)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self.stream = stream
+        self.ctx = gd_init(self.params, self.m, xt, vt, self.workspace, stream)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            gd_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def state(self):
+        """(x, v, a, jerk, t_i, dt_i, t_now) as device tensors (+ float)."""
+        dev = self.m.device
+        x, v, a, j = (torch.empty(self.n, 3, dtype=torch.float64, device=dev) for _ in range(4))
+        t_i, dt_i = (torch.empty(self.n, dtype=torch.float64, device=dev) for _ in range(2))
+        t_now = gd_get_state(self.ctx, x, v, a, j, t_i, dt_i)
+        return x, v, a, j, t_i, dt_i, t_now

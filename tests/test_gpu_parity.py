@@ -1,0 +1,236 @@
+"""Parity of the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Force/jerk tolerance: max relative error 1e-12 per particle (Euclidean norm
+of the error over the norm of the oracle's vector), against the oracle's
+compensated sums. Elementwise steps (prediction, correction) are compared at
+1e-13 relative, a few ulps of FMA-versus-separate rounding. Integer results
+(active sets, times in ticks, block levels, step counts) are compared exactly.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1702_00440_amd import gravidy as g
+from synth_inputs import kepler_pair, plummer
+from tests.gpu_util import DEV, dev, host, rel_err_rows
+
+pytestmark = pytest.mark.gpu
+
+EPS, ETA, DTMAX, DTMIN = 1e-4, 0.01, 0.125, 2.0 ** -22
+F_TOL = 1e-12
+
+
+def _force_gpu(cl, idx, t=None):
+    """Forces of idx on the state predicted to t (explicit time)."""
+    g.gd_predict(cl.ctx, 0.0 if t is None else t)
+    idx_t = dev(idx, torch.int32)
+    acc = torch.empty(len(idx), 3, dtype=torch.float64, device=DEV)
+    jrk = torch.empty(len(idx), 3, dtype=torch.float64, device=DEV)
+    g.gd_force(cl.ctx, idx_t, acc, jrk)
+    return host(acc), host(jrk)
+
+
+@pytest.mark.parametrize("n,seed", [(3, 1), (257, 2), (1000, 3), (1024, 1), (1531, 4)])
+def test_initial_force_all_particles(n, seed):
+    """gd_init's O(N^2) force of every particle (ragged n, several tiles)."""
+    m, x, v = plummer(n, seed)
+    cl = g.Cluster(m, x, v, eta=ETA, eps=EPS, dt_max=DTMAX, dt_min=DTMIN, device=DEV)
+    _, _, a, j, t_i, dt_i, t_now = cl.state()
+    ra, rj = oracle.force(m, x, v, EPS, compensated=True, threads=8)
+    assert rel_err_rows(host(a), ra).max() <= F_TOL
+    assert rel_err_rows(host(j), rj).max() <= F_TOL
+    assert t_now == 0.0 and np.all(host(t_i) == 0.0)
+    cl.close()
+
+
+@pytest.mark.parametrize("n_act", [1, 2, 7, 64, 100, 513, 1000, 4096])
+def test_force_active_subsets(n_act):
+    """Explicit index lists of every size class (each picks a different
+    lane layout), with repeats, on a 4096-particle Plummer sphere."""
+    n = 4096
+    m, x, v = plummer(n, 5)
+    cl = g.Cluster(m, x, v, eta=ETA, eps=EPS, device=DEV)
+    rng = np.random.default_rng(n_act)
+    idx = rng.integers(0, n, n_act)
+    if n_act > 3:
+        idx[1] = idx[0]  # repeated entry
+    acc, jrk = _force_gpu(cl, idx)
+    ra, rj = oracle.force(m, x, v, EPS, idx=idx, compensated=True, threads=8)
+    assert rel_err_rows(acc, ra).max() <= F_TOL
+    assert rel_err_rows(jrk, rj).max() <= F_TOL
+    cl.close()
+
+
+def test_force_on_predicted_state():
+    """Prediction to an explicit time, then force: compared with the
+    oracle's predictor (fed the GPU's own a and jerk) and force."""
+    n = 2048
+    m, x, v = plummer(n, 6)
+    cl = g.Cluster(m, x, v, eta=ETA, eps=EPS, device=DEV)
+    xs, vs, a, j, t_i, _, _ = cl.state()
+    t = 0.0078125
+    idx = np.arange(0, n, 3)
+    acc, jrk = _force_gpu(cl, idx, t)
+    xp, vp = oracle.predict(host(xs), host(vs), host(a), host(j), host(t_i), t)
+    ra, rj = oracle.force(m, xp, vp, EPS, idx=idx, compensated=True, threads=8)
+    assert rel_err_rows(acc, ra).max() <= F_TOL
+    assert rel_err_rows(jrk, rj).max() <= F_TOL
+    cl.close()
+
+
+def test_force_unsoftened_kepler():
+    """eps = 0 takes the kernel variant that masks the self pair; circular
+    orbit closed form a = -w^2 x, jerk = -w^2 v."""
+    m, x, v = kepler_pair(0.3, 0.7, a=1.5, e=0.0)
+    cl = g.Cluster(m, x, v, eta=ETA, eps=0.0, device=DEV)
+    _, _, a, j, _, _, _ = cl.state()
+    w2 = 1.0 / 1.5 ** 3
+    np.testing.assert_allclose(host(a), -w2 * x, rtol=1e-13, atol=1e-16)
+    np.testing.assert_allclose(host(j), -w2 * v, rtol=1e-13, atol=1e-16)
+    cl.close()
+
+
+def test_force_unsoftened_plummer():
+    n = 700
+    m, x, v = plummer(n, 8)
+    cl = g.Cluster(m, x, v, eta=ETA, eps=0.0, device=DEV)
+    _, _, a, j, _, _, _ = cl.state()
+    ra, rj = oracle.force(m, x, v, 0.0, compensated=True)
+    assert rel_err_rows(host(a), ra).max() <= F_TOL
+    assert rel_err_rows(host(j), rj).max() <= F_TOL
+    cl.close()
+
+
+def test_initial_steps_and_energy():
+    """Initial block steps equal the oracle's, energy to 1e-13."""
+    n = 1024
+    m, x, v = plummer(n, 1)
+    cl = g.Cluster(m, x, v, eta=ETA, eps=EPS, device=DEV)
+    ref = oracle.State(m, x, v, EPS, ETA, DTMAX, DTMIN, threads=8)
+    _, _, _, _, _, dt_i, _ = cl.state()
+    np.testing.assert_array_equal(host(dt_i), ref.dt_i)
+    ek, ep, eu = g.gd_energy(cl.ctx, unsoftened=True)
+    rk, rp, ru = oracle.energy(m, x, v, EPS, unsoftened=True)
+    assert ek == pytest.approx(rk, rel=1e-13)
+    assert ep == pytest.approx(rp, rel=1e-13)
+    assert eu == pytest.approx(ru, rel=1e-13)
+    assert g.gd_stats_get(cl.ctx)["e0"] == pytest.approx(rk + rp, rel=1e-13)
+    cl.close()
+
+
+def _oracle_from_gpu(cl, m):
+    xs, vs, a, j, t_i, dt_i, t_now = cl.state()
+    return oracle.State.from_arrays(m, host(xs), host(vs), host(a), host(j), host(t_i), host(dt_i),
+                                    t_now, EPS, ETA, DTMAX, DTMIN, threads=8)
+
+
+@pytest.mark.parametrize("n", [1024, 4096])
+def test_block_step_parity_from_identical_state(n):
+    """Each block step from the same state: identical active set, times and
+    levels; positions, velocities, acceleration and jerk within tolerance."""
+    m, x, v = plummer(n, 2)
+    cl = g.Cluster(m, x, v, eta=ETA, eps=EPS, device=DEV)
+    sizes = []
+    for step in range(40):
+        ref = _oracle_from_gpu(cl, m)
+        act_ref = ref.block_step()
+        g.gd_predict(cl.ctx)
+        idx = torch.empty(n, dtype=torch.int32, device=DEV)
+        n_act = g.gd_active(cl.ctx, idx)
+        assert n_act == len(act_ref)
+        np.testing.assert_array_equal(np.sort(host(idx[:n_act])), act_ref)
+        g.gd_force(cl.ctx)
+        g.gd_correct(cl.ctx)
+        xs, vs, a, j, t_i, dt_i, t_now = cl.state()
+        assert t_now == ref.t_now
+        np.testing.assert_array_equal(host(t_i), ref.t_i)
+        np.testing.assert_array_equal(host(dt_i), ref.dt_i)
+        assert rel_err_rows(host(xs), ref.x).max() <= 1e-13
+        assert rel_err_rows(host(vs), ref.v).max() <= 1e-13
+        assert rel_err_rows(host(a)[act_ref], ref.a[act_ref]).max() <= F_TOL
+        assert rel_err_rows(host(j)[act_ref], ref.jk[act_ref]).max() <= F_TOL
+        sizes.append(n_act)
+    assert min(sizes) < max(sizes)
+    cl.close()
+
+
+def test_full_run_n1024_against_oracle():
+    """Plummer N = 1024 to t = 1 (eps 1e-4, eta 0.01, dt_max 1/8): same number
+    of block and particle steps, energy drift under 1e-6, final state close
+    (the trajectories separate only through rounding over 1 time unit)."""
+    n = 1024
+    m, x, v = plummer(n, 1)
+    cl = g.Cluster(m, x, v, eta=ETA, eps=EPS, device=DEV)
+    st = g.gd_step_to(cl.ctx, 1.0)
+    ref = oracle.State(m, x, v, EPS, ETA, DTMAX, DTMIN, threads=8)
+    rows = ref.run(1.0)
+    assert st["t"] == 1.0
+    assert st["block_steps"] == ref.stats[0]
+    assert st["particle_steps"] == ref.stats[1]
+    assert st["pair_interactions"] == ref.stats[2]
+    assert st["dtmin_clamps"] == ref.stats[3]
+    assert abs(st["e"] - st["e0"]) / abs(st["e0"]) < 1e-6
+    assert st["e"] == pytest.approx(rows[-1, 3], rel=1e-11)
+    xs = host(cl.state()[0])
+    assert np.abs(xs - ref.x).max() < 1e-8
+    cl.close()
+
+
+def test_deterministic_and_resumable():
+    """Two runs are bitwise identical; stopping at t = 0.25, saving the state
+    and resuming in a new context reproduces the uninterrupted run bitwise."""
+    n = 2048
+    m, x, v = plummer(n, 3)
+    a = g.Cluster(m, x, v, eta=ETA, eps=EPS, device=DEV)
+    g.gd_step_to(a.ctx, 0.5)
+    sa = [host(t) for t in a.state()[:6]]
+    b = g.Cluster(m, x, v, eta=ETA, eps=EPS, device=DEV)
+    g.gd_step_to(b.ctx, 0.25)
+    saved = b.state()
+    c = g.Cluster(m, x, v, eta=ETA, eps=EPS, device=DEV)
+    g.gd_set_state(c.ctx, *saved[:6], saved[6])
+    g.gd_step_to(c.ctx, 0.5)
+    g.gd_step_to(b.ctx, 0.5)
+    for cl in (b, c):
+        for u, w in zip(sa, [host(t) for t in cl.state()[:6]]):
+            np.testing.assert_array_equal(u, w)
+    for cl in (a, b, c):
+        cl.close()
+
+
+def test_error_paths():
+    n = 64
+    m, x, v = plummer(n, 4)
+    bad = x.copy()
+    bad[5, 1] = np.nan
+    with pytest.raises(g.GdError) as e:
+        g.Cluster(m, bad, v, device=DEV)
+    assert e.value.status == g.GD_EINVAL
+    cl = g.Cluster(m, x, v, device=DEV)
+    with pytest.raises(g.GdError) as e:
+        g.gd_correct(cl.ctx)
+    assert e.value.status == g.GD_ESTATE
+    with pytest.raises(g.GdError) as e:
+        g.gd_force(cl.ctx)
+    assert e.value.status == g.GD_ESTATE
+    g.gd_predict(cl.ctx)
+    with pytest.raises(g.GdError) as e:
+        g.gd_step_to(cl.ctx, 0.125)
+    assert e.value.status == g.GD_ESTATE
+    g.gd_force(cl.ctx)
+    g.gd_correct(cl.ctx)
+    with pytest.raises(g.GdError) as e:
+        g.gd_energy(cl.ctx)
+    assert e.value.status == g.GD_ESTATE
+    with pytest.raises(g.GdError) as e:
+        g.gd_step_to(cl.ctx, 0.1)
+    assert e.value.status == g.GD_EINVAL
+    g.gd_predict(cl.ctx, 0.0)
+    with pytest.raises(g.GdError) as e:
+        g.gd_force(cl.ctx, dev(np.array([0, n]), torch.int32))
+    assert e.value.status == g.GD_EINVAL
+    st = g.gd_step_to(cl.ctx, 0.125)
+    assert st["t"] == 0.125
+    g.gd_energy(cl.ctx)
+    cl.close()

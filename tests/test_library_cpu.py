@@ -1,0 +1,108 @@
+"""CPU-side checks of the HIP library: it is built for gfx950, it exports
+every entry point the public header declares, and the host-side argument
+checks answer without touching a GPU."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+import torch  # noqa: F401  (binds the library to torch's HIP runtime)
+
+from paper_1702_00440_amd import gravidy as g
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gravidy_hip.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(gd_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for want in ["gd_init", "gd_predict", "gd_force", "gd_correct", "gd_step_to", "gd_energy",
+                 "gd_workspace_bytes", "gd_active", "gd_get_state", "gd_set_state", "gd_stats_get",
+                 "gd_destroy", "gd_last_error"]:
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol():
+    assert os.path.exists(g.LIB_PATH), "run the build first"
+    out = subprocess.run(["nm", "-D", "--defined-only", g.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(re.findall(r"\bT (gd_[a-z_]+)\b", out))
+    missing = [n for n in _declared() if n not in exported]
+    assert not missing, missing
+    lib = g.library()
+    for n in _declared():
+        assert hasattr(lib, n)
+
+
+def test_library_has_gfx950_code_object():
+    data = open(g.LIB_PATH, "rb").read()
+    assert b"gfx950" in data
+
+
+def test_workspace_bytes_host_only():
+    b1 = g.gd_workspace_bytes(1024)
+    b2 = g.gd_workspace_bytes(16384)
+    assert b2 > b1 > 1024 * 8 * 25
+    assert b1 % 256 == 0
+    with pytest.raises(g.GdError) as e:
+        g.gd_workspace_bytes(1)
+    assert e.value.status == g.GD_EINVAL
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(eta=0.0), "eta"),
+    (dict(eta=float("nan")), "eta"),
+    (dict(eps=-1.0), "eps"),
+    (dict(eps=1e-40), "eps"),
+    (dict(dt_max=0.1), "power"),
+    (dict(dt_min=0.25), "power"),
+    (dict(dt_min=2.0 ** -60), "40"),
+    (dict(flags=1), "flags"),
+])
+def test_init_rejects_bad_params_before_any_device_work(kw, msg):
+    """Parameter validation happens on the host before any HIP call, so it can
+    run here with dummy (never dereferenced) pointers."""
+    lib = g.library()
+    p = g.make_params(**kw)
+    ctx = C.c_void_p()
+    dummy = C.c_void_p(256)
+    rc = lib.gd_init(C.byref(ctx), C.byref(p), 16, dummy, dummy, dummy, dummy, 1 << 30, None)
+    assert rc == g.GD_EINVAL
+    assert not ctx.value
+    assert msg in g.gd_last_error(None)
+
+
+def test_init_rejects_short_workspace_and_null():
+    lib = g.library()
+    p = g.make_params()
+    ctx = C.c_void_p()
+    dummy = C.c_void_p(256)
+    need = g.gd_workspace_bytes(16)
+    rc = lib.gd_init(C.byref(ctx), C.byref(p), 16, dummy, dummy, dummy, dummy, need - 1, None)
+    assert rc == g.GD_ENOMEM
+    rc = lib.gd_init(C.byref(ctx), C.byref(p), 16, None, dummy, dummy, dummy, need, None)
+    assert rc == g.GD_EINVAL
+    rc = lib.gd_init(C.byref(ctx), C.byref(p), 1, dummy, dummy, dummy, dummy, need, None)
+    assert rc == g.GD_EINVAL
+    misaligned = C.c_void_p(256 + 8)
+    rc = lib.gd_init(C.byref(ctx), C.byref(p), 16, dummy, dummy, dummy, misaligned, need, None)
+    assert rc == g.GD_EINVAL
+
+
+def test_null_context_is_rejected():
+    lib = g.library()
+    assert lib.gd_predict(None, None) == g.GD_EINVAL
+    assert lib.gd_correct(None) == g.GD_EINVAL
+    assert lib.gd_step_to(None, 1.0, None) == g.GD_EINVAL
+    lib.gd_destroy(None)
+
+
+def test_binding_refuses_host_tensors():
+    with pytest.raises(TypeError):
+        g._ptr(torch.zeros(3, dtype=torch.float64), torch.float64)
