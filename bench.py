@@ -1,0 +1,193 @@
+#!/usr/bin/env python
+"""Throughput benchmark of the Hermite-4 block-step path on one MI355X.
+
+One step = one whole integration of the workload from its initial
+conditions: the O(N^2) initial force, block steps (predict, force, correct)
+to t_end, and the energy at every multiple of dt_max. Default workload:
+equal-mass Plummer sphere, N = 16384, eps = 1e-4, eta = 0.01, dt_max = 1/8,
+t = 0 -> 1, FP64. Inputs are resident in device memory before the timed
+region; the context and workspace are created once (gd_reinit restarts the
+integration from the initial conditions inside each step).
+
+Prints one JSON line: the metric is force pair interactions per second
+(N_act * N per block step, plus N^2 for the initial force) over the timed
+steps, with the energy drift, the roofline of the force kernel and the CPU
+oracle timed on a bounded sample of the same workload.
+
+Roofline: 60 flops per acceleration+jerk pair against the FP64 vector peak.
+The force kernel's per-launch durations come from HIP events that record
+each launch's own start and end (hipExtLaunchKernelGGL) during one more
+integration of the same workload right after the timed steps; in that pass
+the steps are launched directly rather than replayed from a graph, which
+changes the gaps between kernels but not the kernels.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FLOPS_PER_PAIR = 60
+PEAK_FP64_VECTOR_TFLOPS = 78.6
+
+
+def cpu_baseline(w, seconds):
+    """The oracle on a bounded sample of the workload: its O(N^2) initial
+    force, then block steps from t = 0 until about `seconds` of wall time."""
+    import oracle
+    from synth_inputs import plummer
+
+    m, x, v = plummer(w["n"], w["seed"])
+    threads = oracle.max_threads()
+    t0 = time.perf_counter()
+    s = oracle.State(m, x, v, w["eps"], w["eta"], w["dt_max"], w["dt_min"], threads=threads)
+    pairs = w["n"] * w["n"]
+    nsteps = 0
+    while time.perf_counter() - t0 < seconds and s.t_now < w["t_end"]:
+        act = s.block_step()
+        pairs += len(act) * w["n"]
+        nsteps += 1
+    el = time.perf_counter() - t0
+    return {
+        "value": pairs / el,
+        "unit": "pair-interactions/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": (f"initial O(N^2) force + first {nsteps} block steps (to t={s.t_now:.6g}) of the "
+                   f"same workload; {pairs:.3e} pairs in {el:.1f} s"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="plummer_n16384")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true", help="skip the force-launch event timing")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only copy BYTES of device memory once (calibrates HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; --gpus must be 1 "
+              "(the multi-GPU split is described, not built).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    if args.copy_probe:
+        # One plain device-to-device copy of a known size: under rocprofv3
+        # --pmc FETCH_SIZE / WRITE_SIZE its kernel reads the counter values that
+        # correspond to copy_bytes read and written.
+        nel = args.copy_probe // 8
+        src = torch.arange(nel, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": nel * 8, "check": float(dst[-1].item())}), flush=True)
+        return
+
+    from paper_1702_00440_amd import gravidy as g
+    from synth_inputs import WORKLOADS, plummer
+
+    w = WORKLOADS[args.workload]
+    n, t_end, dt_max = w["n"], w["t_end"], w["dt_max"]
+    dev = torch.device("cuda:0")
+    m_h, x_h, v_h = plummer(n, w["seed"])
+    m = torch.as_tensor(m_h).to(dev)
+    x = torch.as_tensor(x_h).to(dev).contiguous()
+    v = torch.as_tensor(v_h).to(dev).contiguous()
+    cl = g.Cluster(m_h, x_h, v_h, eta=w["eta"], eps=w["eps"], dt_max=dt_max, dt_min=w["dt_min"], device=dev)
+    ctx = cl.ctx
+    n_chunks = int(round(t_end / dt_max))
+
+    def one_step():
+        g.gd_reinit(ctx, m, x, v)
+        drift = 0.0
+        st = None
+        for k in range(1, n_chunks + 1):
+            st = g.gd_step_to(ctx, k * dt_max)
+            drift = max(drift, abs(st["e"] - st["e0"]) / abs(st["e0"]))
+        return st, drift
+
+    for _ in range(args.warmup):
+        one_step()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    pairs = 0
+    drift = 0.0
+    stats = None
+    for _ in range(args.steps):
+        stats, d = one_step()
+        pairs += stats["pair_interactions"] + n * n
+        drift = max(drift, d)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    elapsed = max(wall, gpu_ms / 1e3)
+    prof = {"force_ms": 0.0, "launches": 0, "pairs": 0}
+    if not args.no_profile:
+        g.gd_profile_force(ctx, True)
+        one_step()
+        prof = g.gd_profile_get(ctx)
+        g.gd_profile_force(ctx, False)
+    launches = max(prof["launches"], 1)
+    avg_s = prof["force_ms"] / 1e3 / launches
+    flops_per_launch = FLOPS_PER_PAIR * prof["pairs"] / launches
+    achieved = flops_per_launch / avg_s / 1e12 if avg_s > 0 else 0.0
+
+    out = {
+        "metric": "pair-interactions/s (acc+jerk)",
+        "value": pairs / elapsed,
+        "unit": "pair-interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}_fp64_t{t_end:g}",
+            "n": n, "eps": w["eps"], "eta": w["eta"], "dt_max": dt_max, "dt_min": w["dt_min"],
+            "t_end": t_end, "seed": w["seed"],
+            "ic": "equal-mass Plummer sphere (Aarseth-Henon-Wielen sampling), Henon units",
+        },
+        "energy_drift": drift,
+        "block_steps": stats["block_steps"],
+        "particle_steps": stats["particle_steps"],
+        "pairs_per_step": stats["pair_interactions"] + n * n,
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": PEAK_FP64_VECTOR_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_VECTOR_TFLOPS,
+            "traffic": None,
+            "kernel": "k_force<false> (FP64 acc+jerk)",
+            "launches": prof["launches"],
+            "avg_launch_us": avg_s * 1e6,
+            "flops_per_launch": flops_per_launch,
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    cl.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

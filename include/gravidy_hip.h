@@ -94,6 +94,28 @@ gd_status gd_init(gd_ctx** ctx, const gd_params* p, int64_t n, const double* m, 
                   const double* v, void* workspace, size_t ws_bytes, void* hip_stream);
 
 /*
+ * Restart an existing context from new masses, positions and velocities of
+ * the same n (device arrays as in gd_init), at t = 0: the same steps as
+ * gd_init (initial force, block steps, energy) without creating host
+ * resources; captured graphs are kept. Statistics restart from zero.
+ * Synchronises. Errors as gd_init (GD_EINVAL, GD_ENONFINITE, GD_EHIP).
+ */
+gd_status gd_reinit(gd_ctx* c, const double* m, const double* x, const double* v);
+
+/*
+ * Force-kernel timing. With enable != 0, gd_step_to runs its block steps as
+ * direct launches on the context's stream instead of graph replays, and
+ * every force launch issued by gd_reinit and gd_step_to records its own
+ * start and end in HIP events (hipExtLaunchKernelGGL); the elapsed times of
+ * the launches that did work are summed. Counters restart at zero on every
+ * call. gd_profile_get reports the summed milliseconds, the number of such
+ * launches, and their pair interactions (N_act * N each). Host outputs; any
+ * may be NULL. Results are identical with and without timing.
+ */
+gd_status gd_profile_force(gd_ctx* c, int enable);
+gd_status gd_profile_get(gd_ctx* c, double* force_ms, int64_t* launches, int64_t* pairs);
+
+/*
  * Prediction of all particles (Sec. 2.4, steps 5 and 7(a)).
  * t == NULL: find the next block time t_next (the earliest t_i + dt_i),
  * mark the active particles (t_i + dt_i == t_next), and predict every particle
@@ -112,9 +134,10 @@ gd_status gd_predict(gd_ctx* c, const double* t);
  * idx == NULL: the active set of the last gd_predict(NULL); n_act is ignored
  * and acc/jerk, if given, must hold n rows (the first N_act rows are written,
  * in the order of gd_active).
- * idx != NULL: n_act device int32 indices in [0, n) (repeats allowed).
+ * idx != NULL: n_act device int32 indices in [0, n) (repeats allowed); the
+ * call synchronises to check them.
  * acc, jerk: device (n_act, 3) outputs, or NULL to keep the result internal
- * (as gd_correct needs it). Queues work only.
+ * (as gd_correct needs it). Queues work only when idx == NULL.
  * Errors: GD_ESTATE before any gd_predict, or idx == NULL after gd_predict(t);
  * GD_EINVAL for n_act < 0 or > n; GD_EHIP.
  */

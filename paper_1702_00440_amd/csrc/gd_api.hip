@@ -33,7 +33,8 @@ size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // Byte offsets of every array in the workspace.
 struct Layout {
-  size_t sc, m, x[3], v[3], a[3], j[3], p[3], pv[3], tick, lev, active, part, ebuf, total;
+  size_t sc, m, x[3], v[3], a[3], j[3], p[3], pv[3], tick, lev, active, ip[3], ipv[3], ia[3], ij[3], ilev,
+      part, ebuf, total;
 };
 
 Layout make_layout(long long n) {
@@ -56,6 +57,11 @@ Layout make_layout(long long n) {
   L.tick = take(sizeof(long long) * (size_t)n);
   L.lev = take(sizeof(int) * (size_t)n);
   L.active = take(sizeof(int) * (size_t)n);
+  for (int d = 0; d < 3; ++d) L.ip[d] = take(nd);
+  for (int d = 0; d < 3; ++d) L.ipv[d] = take(nd);
+  for (int d = 0; d < 3; ++d) L.ia[d] = take(nd);
+  for (int d = 0; d < 3; ++d) L.ij[d] = take(nd);
+  L.ilev = take(sizeof(int) * (size_t)n);
   L.part = take(sizeof(double) * 6 * (size_t)partial_rows(n));
   const long long eitems = std::max<long long>((n + kBlock - 1) / kBlock, kEnergyGrid);
   L.ebuf = take(sizeof(double) * 3 * (size_t)(eitems + 1));
@@ -79,6 +85,10 @@ struct gd_ctx {
   hipStream_t stream = nullptr;
   hipStream_t capture_stream = nullptr;
   hipGraphExec_t graph = nullptr;
+  bool prof = false, ev_ready = false;
+  hipEvent_t ev_s[kGraphSteps + 1] = {}, ev_e[kGraphSteps + 1] = {};
+  double prof_ms = 0.0;
+  long long prof_launches = 0, prof_pairs = 0;
   Sched* h_sc = nullptr;    // pinned host mirror of the device record
   double* h_e = nullptr;    // pinned host energy result (3 doubles)
   double* d_eres = nullptr; // device energy result
@@ -127,29 +137,63 @@ gd_status energy_now(gd_ctx* c, int unsoft, double out[3]) {
   return GD_OK;
 }
 
-// One block step: predict (auto schedule), force, correct.
-gd_status enqueue_step(gd_ctx* c, hipStream_t s) {
+// One block step: predict (auto schedule), force, correct. With events
+// (direct launches only), the force launch records its own start and end.
+gd_status enqueue_step(gd_ctx* c, hipStream_t s, hipEvent_t ev_s, hipEvent_t ev_e) {
   GD_TRY(c->hip(launch_predict(c->d, c->c, kPredAuto, 0.0, s), "predict kernel"));
-  GD_TRY(c->hip(launch_force(c->d, c->c, s), "force kernel"));
+  GD_TRY(c->hip(launch_force(c->d, c->c, s, ev_s, ev_e), "force kernel"));
   return c->hip(launch_correct(c->d, c->c, s), "correct kernel");
 }
 
-gd_status build_graph(gd_ctx* c) {
-  if (c->graph) return GD_OK;
+// Captures kGraphSteps block steps into *out.
+gd_status build_graph(gd_ctx* c, hipGraphExec_t* out) {
+  if (*out) return GD_OK;
   hipGraph_t g = nullptr;
   GD_TRY(c->hip(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal),
                 "begin capture"));
   gd_status st = GD_OK;
-  for (int k = 0; k < kGraphSteps && st == GD_OK; ++k) st = enqueue_step(c, c->capture_stream);
+  for (int k = 0; k < kGraphSteps && st == GD_OK; ++k)
+    st = enqueue_step(c, c->capture_stream, nullptr, nullptr);
   hipError_t e = hipStreamEndCapture(c->capture_stream, &g);
   if (st != GD_OK) {
     if (g) (void)hipGraphDestroy(g);
     return st;
   }
   GD_TRY(c->hip(e, "end capture"));
-  e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+  e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   return c->hip(e, "instantiate graph");
+}
+
+// Initialisation (Sec. 2.4 steps 2-3): load m, x, v at t = 0, force of every
+// particle (O(N^2)), initial block steps, energy. Shared by gd_init and
+// gd_reinit; statistics restart from zero.
+gd_status initialise(gd_ctx* c, const double* m, const double* x, const double* v) {
+  const Dev& d = c->d;
+  GD_TRY(c->hip(launch_reset_sched(d, 0, c->stream), "reset"));
+  GD_TRY(c->hip(launch_load(d, c->c, m, x, v, c->stream), "load kernel"));
+  GD_TRY(c->hip(launch_predict(d, c->c, kPredAll, 0.0, c->stream), "predict kernel"));
+  GD_TRY(c->hip(launch_force(d, c->c, c->stream, c->prof ? c->ev_s[kGraphSteps] : nullptr,
+                             c->prof ? c->ev_e[kGraphSteps] : nullptr),
+                "force kernel"));
+  GD_TRY(c->hip(launch_init_dt(d, c->c, c->stream), "init dt kernel"));
+  GD_TRY(read_sched(c));
+  if (c->h_sc->bad_input) return c->fail(GD_EINVAL, "non-finite or negative input (m, x or v)");
+  if (c->h_sc->nonfinite) return c->fail(GD_ENONFINITE, "non-finite initial acceleration or jerk");
+  if (c->prof) {
+    float ms = 0.f;
+    GD_TRY(c->hip(hipEventElapsedTime(&ms, c->ev_s[kGraphSteps], c->ev_e[kGraphSteps]), "event time"));
+    c->prof_ms += ms;
+    c->prof_launches += 1;
+    c->prof_pairs += c->n * c->n;
+  }
+  double e[3];
+  GD_TRY(energy_now(c, 0, e));
+  c->e0 = c->e_last = e[0] + e[1];
+  c->t_now = 0;
+  c->synced = true;
+  c->phase = kIdle;
+  return GD_OK;
 }
 
 }  // namespace
@@ -195,6 +239,7 @@ gd_status gd_init(gd_ctx** out, const gd_params* p, int64_t n, const double* m, 
   c->c.dt_max = p->dt_max;
   c->c.eta = p->eta;
   c->c.eps2 = p->eps * p->eps;
+  launch_grids((int)n, &c->c.force_grid, &c->c.correct_grid);
   c->stream = (hipStream_t)hip_stream;
   char* w = (char*)workspace;
   Dev& d = c->d;
@@ -217,6 +262,17 @@ gd_status gd_init(gd_ctx** out, const gd_params* p, int64_t n, const double* m, 
   d.tick = (long long*)(w + L.tick);
   d.lev = (int*)(w + L.lev);
   d.active = (int*)(w + L.active);
+  double** is[3] = {&d.ix, &d.iy, &d.iz};
+  double** ivs[3] = {&d.ivx, &d.ivy, &d.ivz};
+  double** ias[3] = {&d.iax, &d.iay, &d.iaz};
+  double** ijs[3] = {&d.ijx, &d.ijy, &d.ijz};
+  for (int k = 0; k < 3; ++k) {
+    *is[k] = (double*)(w + L.ip[k]);
+    *ivs[k] = (double*)(w + L.ipv[k]);
+    *ias[k] = (double*)(w + L.ia[k]);
+    *ijs[k] = (double*)(w + L.ij[k]);
+  }
+  d.ilev = (int*)(w + L.ilev);
   d.part = (double*)(w + L.part);
   d.ebuf = (double*)(w + L.ebuf);
 
@@ -236,34 +292,39 @@ gd_status gd_init(gd_ctx** out, const gd_params* p, int64_t n, const double* m, 
                    "capture stream")) != GD_OK)
     return cleanup_fail(st);
 
-  // Initialisation (Sec. 2.4 steps 2-3): load, forces of everyone at t = 0,
-  // initial steps, energy.
-  if ((st = c->hip(launch_reset_sched(d, 0, c->stream), "reset")) != GD_OK) return cleanup_fail(st);
-  if ((st = c->hip(launch_load(d, c->c, m, x, v, c->stream), "load kernel")) != GD_OK)
-    return cleanup_fail(st);
-  if ((st = c->hip(launch_predict(d, c->c, kPredAll, 0.0, c->stream), "predict kernel")) != GD_OK)
-    return cleanup_fail(st);
-  if ((st = c->hip(launch_force(d, c->c, c->stream), "force kernel")) != GD_OK) return cleanup_fail(st);
-  if ((st = c->hip(launch_init_dt(d, c->c, c->stream), "init dt kernel")) != GD_OK)
-    return cleanup_fail(st);
-  if ((st = read_sched(c)) != GD_OK) return cleanup_fail(st);
-  if (c->h_sc->bad_input) {
-    c->err = "non-finite or negative input (m, x or v)";
-    return cleanup_fail(GD_EINVAL);
-  }
-  if (c->h_sc->nonfinite) {
-    c->err = "non-finite initial acceleration or jerk";
-    return cleanup_fail(GD_ENONFINITE);
-  }
-  // Device energy result follows the energy partials.
   c->d_eres = d.ebuf + 3 * (size_t)make_eplan((int)n).items;
-  double e[3];
-  if ((st = energy_now(c, 0, e)) != GD_OK) return cleanup_fail(st);
-  c->e0 = c->e_last = e[0] + e[1];
-  c->t_now = 0;
-  c->synced = true;
-  c->phase = kIdle;
+  if ((st = initialise(c, m, x, v)) != GD_OK) return cleanup_fail(st);
   *out = c;
+  return GD_OK;
+}
+
+gd_status gd_reinit(gd_ctx* c, const double* m, const double* x, const double* v) {
+  if (!c) return GD_EINVAL;
+  if (!m || !x || !v) return c->fail(GD_EINVAL, "NULL argument");
+  return initialise(c, m, x, v);
+}
+
+gd_status gd_profile_force(gd_ctx* c, int enable) {
+  if (!c) return GD_EINVAL;
+  if (enable && !c->ev_ready) {
+    for (int k = 0; k < kGraphSteps + 1; ++k) {
+      GD_TRY(c->hip(hipEventCreate(&c->ev_s[k]), "event create"));
+      GD_TRY(c->hip(hipEventCreate(&c->ev_e[k]), "event create"));
+    }
+    c->ev_ready = true;
+  }
+  c->prof = enable != 0;
+  c->prof_ms = 0.0;
+  c->prof_launches = 0;
+  c->prof_pairs = 0;
+  return GD_OK;
+}
+
+gd_status gd_profile_get(gd_ctx* c, double* force_ms, int64_t* launches, int64_t* pairs) {
+  if (!c) return GD_EINVAL;
+  if (force_ms) *force_ms = c->prof_ms;
+  if (launches) *launches = c->prof_launches;
+  if (pairs) *pairs = c->prof_pairs;
   return GD_OK;
 }
 
@@ -284,11 +345,9 @@ gd_status gd_predict(gd_ctx* c, const double* t) {
 gd_status gd_force(gd_ctx* c, const int32_t* idx, int64_t n_act, double* acc, double* jerk) {
   if (!c) return GD_EINVAL;
   if (c->phase == kIdle) return c->fail(GD_ESTATE, "gd_force before gd_predict");
-  int rows;
   if (idx == nullptr) {
     if (c->phase != kPredictedAuto && c->phase != kForcedAuto)
       return c->fail(GD_ESTATE, "no active set: use gd_predict(NULL) or pass indices");
-    rows = (int)c->n;
     c->phase = kForcedAuto;
   } else {
     if (n_act < 0 || n_act > c->n) return c->fail(GD_EINVAL, "n_act out of range");
@@ -297,12 +356,10 @@ gd_status gd_force(gd_ctx* c, const int32_t* idx, int64_t n_act, double* acc, do
       return GD_OK;
     }
     GD_TRY(c->hip(launch_set_active(c->d, c->c, idx, (int)n_act, c->stream), "set active"));
-    rows = (int)n_act;
     c->phase = kForcedExplicit;
   }
   GD_TRY(c->hip(launch_force(c->d, c->c, c->stream), "force kernel"));
-  if (acc || jerk)
-    GD_TRY(c->hip(launch_gather_forces(c->d, c->c, rows, acc, jerk, c->stream), "gather forces"));
+  if (acc || jerk) GD_TRY(c->hip(launch_reduce_out(c->d, c->c, acc, jerk, c->stream), "force output"));
   if (idx != nullptr) {
     GD_TRY(read_sched(c));
     if (c->h_sc->bad_input) {
@@ -351,16 +408,37 @@ gd_status gd_step_to(gd_ctx* c, double t_end, gd_stats* st) {
   const long long per_max = 1LL << c->c.kmax;
   const long long target = (long long)q * per_max;
   if (target < c->t_now) return c->fail(GD_EINVAL, "t_end is before the current time");
-  GD_TRY(build_graph(c));
+  // Profiling runs the same steps as direct launches (the force launches
+  // carry timing events); otherwise a captured graph is replayed.
+  if (!c->prof) GD_TRY(build_graph(c, &c->graph));
   c->phase = kIdle;
+  GD_TRY(read_sched(c));
+  long long steps_before = c->h_sc->block_steps, pairs_before = c->h_sc->pairs;
   while (c->t_now < target) {
     // Advance to the next multiple of dt_max, where all particles meet.
     const long long chunk_end = (c->t_now / per_max + 1) * per_max;
     GD_TRY(c->hip(launch_set_tend(c->d, chunk_end, c->stream), "prepare"));
     for (;;) {
-      GD_TRY(c->hip(hipGraphLaunch(c->graph, c->stream), "graph launch"));
+      if (c->prof) {
+        for (int k = 0; k < kGraphSteps; ++k) GD_TRY(enqueue_step(c, c->stream, c->ev_s[k], c->ev_e[k]));
+      } else {
+        GD_TRY(c->hip(hipGraphLaunch(c->graph, c->stream), "graph launch"));
+      }
       GD_TRY(read_sched(c));
       if (c->h_sc->nonfinite) return c->fail(GD_ENONFINITE, "non-finite acceleration or jerk");
+      if (c->prof) {
+        // Steps run in order; the first (block_steps delta) of the replay were real.
+        const long long ran = c->h_sc->block_steps - steps_before;
+        for (long long k = 0; k < ran && k < kGraphSteps; ++k) {
+          float ms = 0.f;
+          GD_TRY(c->hip(hipEventElapsedTime(&ms, c->ev_s[k], c->ev_e[k]), "event time"));
+          c->prof_ms += ms;
+        }
+        c->prof_launches += ran;
+        c->prof_pairs += c->h_sc->pairs - pairs_before;
+      }
+      steps_before = c->h_sc->block_steps;
+      pairs_before = c->h_sc->pairs;
       if (c->h_sc->t_now >= chunk_end) break;
     }
     c->t_now = c->h_sc->t_now;
@@ -429,6 +507,11 @@ gd_status gd_stats_get(gd_ctx* c, gd_stats* st) {
 void gd_destroy(gd_ctx* c) {
   if (!c) return;
   if (c->graph) (void)hipGraphExecDestroy(c->graph);
+  if (c->ev_ready)
+    for (int k = 0; k < kGraphSteps + 1; ++k) {
+      (void)hipEventDestroy(c->ev_s[k]);
+      (void)hipEventDestroy(c->ev_e[k]);
+    }
   if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
   if (c->h_sc) (void)hipHostFree(c->h_sc);
   if (c->h_e) (void)hipHostFree(c->h_e);

@@ -15,10 +15,16 @@ constexpr int kTileJ = 256;
 constexpr int kIPerLane = 2;
 // Work items the force decomposition aims for (about 4 workgroups per CU).
 constexpr int kTargetItems = 1024;
-// Fixed force grid: workgroups loop over items beyond it.
-constexpr int kForceGrid = 2048;
+// Upper bound of the force grid: workgroups loop over items beyond it.
+constexpr int kForceGrid = 1024;
+// Upper bound of the corrector grid.
+constexpr int kCorrectGrid = 2048;
 // A lane of the split-j layout keeps at least this many j per slice.
 constexpr int kMinJPerLane = 16;
+// Smallest log2 of the lanes that share one i: i tiles hold at most
+// (kBlock >> kMinLj) * kIPerLane = 32 particles, which keeps the number of
+// j slices (and so the partial sums to reduce) small for large blocks.
+constexpr int kMinLj = 4;
 // Energy: fixed grid of slice items.
 constexpr int kEnergyGrid = 1024;
 // Maximum block-step level (dt = dt_max / 2^level).
@@ -58,7 +64,7 @@ __host__ __device__ inline Plan make_plan(int n_act, int n) {
   Plan p;
   int max_s = (n + kTileJ - 1) / kTileJ;
   if (max_s < 1) max_s = 1;
-  int lj = 0;
+  int lj = kMinLj;
   for (;;) {
     int it = (kBlock >> lj) * kIPerLane;
     int nit = (n_act + it - 1) / it;
@@ -84,9 +90,10 @@ __host__ __device__ inline Plan make_plan(int n_act, int n) {
 }
 
 // Rows of the partial-force buffer a context of n particles needs: for every
-// plan, s * n_act <= s * nit * it <= max(nit, kTargetItems) * it.
+// plan, s * n_act <= s * nit * it <= max(nit, kTargetItems) * it, it <= 32.
 inline long long partial_rows(long long n) {
-  return n + (long long)kBlock * kIPerLane + (long long)kTargetItems * kBlock * kIPerLane;
+  const long long it_max = (long long)(kBlock >> kMinLj) * kIPerLane;
+  return n + it_max + (long long)kTargetItems * it_max;
 }
 
 // Energy decomposition: items are (i tile of kBlock, j slice).
@@ -116,29 +123,63 @@ struct Dev {
   long long* tick;                         // t_i in dt_min ticks
   int* lev;                                // dt_i = dt_max / 2^lev
   int* active;                             // active list (positions 0..n_act-1)
+  double *ix, *iy, *iz, *ivx, *ivy, *ivz;  // predicted state of the active list, by position
+  double *iax, *iay, *iaz, *ijx, *ijy, *ijz;  // a, jerk at t_i of the active list, by position
+  int* ilev;                               // level of the active list, by position
   double* part;                            // [s][6][n_act] partial forces
   double* ebuf;                            // energy partials [kEnergyGrid][3] + result [3]
 };
 
 struct Consts {
   int n;
-  int kmax;        // log2(dt_max / dt_min)
+  int kmax;          // log2(dt_max / dt_min)
+  int force_grid;    // workgroups of a force launch
+  int correct_grid;  // workgroups of a corrector launch
   double dt_min, dt_max, eta, eps2;
 };
+
+// Lanes the corrector gives one active particle: one per j slice of the
+// force plan (rounded up to a power of two), at most a wave.
+__host__ __device__ inline int correct_lanes(int s) {
+  int l = 1;
+  while (l < s && l < 64) l <<= 1;
+  return l;
+}
+
+// Launch sizes for a context of n particles: enough workgroups for the
+// largest force decomposition and corrector layout over all block sizes
+// (sampled), capped; kernels loop over anything beyond the grid.
+inline void launch_grids(int n, int* force_grid, int* correct_grid) {
+  long long fmax = 1, cmax = 1;
+  const int step = n > 8192 ? n / 8192 : 1;
+  for (int a = 1;; a += step) {
+    if (a > n) a = n;
+    const Plan p = make_plan(a, n);
+    if (p.items > fmax) fmax = p.items;
+    const long long lanes = (long long)a * correct_lanes(p.s);
+    const long long wg = (lanes + kBlock - 1) / kBlock;
+    if (wg > cmax) cmax = wg;
+    if (a == n) break;
+  }
+  *force_grid = (int)(fmax < kForceGrid ? fmax : kForceGrid);
+  *correct_grid = (int)(cmax < kCorrectGrid ? cmax : kCorrectGrid);
+}
 
 // Launchers (gd_kernels.hip). Each returns the hipGetLastError() of its launch.
 hipError_t launch_load(const Dev& d, const Consts& c, const double* m, const double* x,
                        const double* v, hipStream_t s);
 hipError_t launch_predict(const Dev& d, const Consts& c, int mode, double t_explicit, hipStream_t s);
-hipError_t launch_force(const Dev& d, const Consts& c, hipStream_t s);
+// ev_start/ev_stop (may be null): events that record the launch's own start
+// and end (hipExtLaunchKernelGGL), for per-launch timing outside graphs.
+hipError_t launch_force(const Dev& d, const Consts& c, hipStream_t s, hipEvent_t ev_start = nullptr,
+                        hipEvent_t ev_stop = nullptr);
 hipError_t launch_correct(const Dev& d, const Consts& c, hipStream_t s);
 hipError_t launch_init_dt(const Dev& d, const Consts& c, hipStream_t s);
+hipError_t launch_reduce_out(const Dev& d, const Consts& c, double* acc, double* jerk, hipStream_t s);
 hipError_t launch_energy(const Dev& d, const Consts& c, int unsoft, hipStream_t s);
 hipError_t launch_set_tend(const Dev& d, long long t_end, hipStream_t s);
 hipError_t launch_reset_sched(const Dev& d, long long t_now, hipStream_t s);
 hipError_t launch_set_active(const Dev& d, const Consts& c, const int32_t* idx, int n_act, hipStream_t s);
-hipError_t launch_gather_forces(const Dev& d, const Consts& c, int n_rows_max, double* acc,
-                                double* jerk, hipStream_t s);
 hipError_t launch_copy_active(const Dev& d, const Consts& c, int32_t* idx, hipStream_t s);
 hipError_t launch_get_state(const Dev& d, const Consts& c, double* x, double* v, double* a,
                             double* jerk, double* t_i, double* dt_i, hipStream_t s);

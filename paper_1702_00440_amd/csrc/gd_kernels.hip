@@ -13,6 +13,8 @@
 // order that depends only on (n_act, n), never on scheduling or on the order
 // of the active list, so results are bitwise reproducible.
 
+#include <hip/hip_ext.h>
+
 #include "gd_internal.h"
 
 namespace gd {
@@ -65,6 +67,26 @@ __device__ __forceinline__ void pair_fp64(double xi, double yi, double zi, doubl
 __device__ __forceinline__ double shfl_xor_d(double v, int mask) { return __shfl_xor(v, mask, 64); }
 
 // ---------------------------------------------------------------------------
+// Block time steps
+// ---------------------------------------------------------------------------
+
+// Smallest k >= 0 with dt_max / 2^k <= dtstar; kmax + 1 when even dt_min is
+// too large (the caller clamps and counts); 0 when dtstar is not a number
+// below dt_max (including +inf and NaN). With dtstar / dt_max = f 2^e,
+// f in [0.5, 1), the answer is exactly 1 - e.
+__device__ __forceinline__ int level_for(double dtstar, double dt_max, int kmax) {
+  if (!(dtstar < dt_max)) return 0;
+  if (!(dtstar > 0.0)) return kmax + 1;
+  int e;
+  (void)frexp(dtstar / dt_max, &e);
+  return min(1 - e, kmax + 1);
+}
+
+__device__ __forceinline__ double norm3(double a, double b, double c) {
+  return sqrt(a * a + b * b + c * c);
+}
+
+// ---------------------------------------------------------------------------
 // Force kernel: O(N_act * N) acceleration and jerk (Sec. 2.4 step 7(c), Sec. 2.5)
 // ---------------------------------------------------------------------------
 //
@@ -73,32 +95,35 @@ __device__ __forceinline__ double shfl_xor_d(double v, int mask) { return __shfl
 // host to know the block size:
 //   - items are (i tile, j slice) pairs; workgroups loop over items;
 //   - inside a workgroup, LJ = 2^lj consecutive lanes share the same i
-//     particles and split the slice's j between them (LJ = 1: pure
-//     i-parallel with LDS broadcast of j; LJ up to 64: split j inside a
-//     wave, for small active blocks);
+//     particles and split the slice's j between them (LJ = 16 for most block
+//     sizes, up to 64 inside one wave);
 //   - each lane holds kIPerLane i particles, so one LDS read of j feeds
 //     several pair evaluations;
 //   - j particles of the slice go through LDS in tiles of kTileJ, loaded
 //     with coalesced SoA reads and prefetched into registers one tile ahead;
 //   - the LJ lanes of one i are reduced with a fixed xor butterfly, and each
-//     slice writes its partial sum to part[slice][component][position];
-//     the corrector sums slices in ascending order.
+//     slice writes its partial sum to part[slice][component][position].
+// The slices of a particle are summed afterwards by the kernel that consumes
+// the force (corrector, initial steps, or output), in an order that depends
+// only on (n_act, n).
 template <bool kMaskSelf>
-__global__ __launch_bounds__(kBlock) void k_force(const Sched* __restrict__ sc, int n, double eps2,
-                                                  const double* __restrict__ px,
-                                                  const double* __restrict__ py,
-                                                  const double* __restrict__ pz,
-                                                  const double* __restrict__ pvx,
-                                                  const double* __restrict__ pvy,
-                                                  const double* __restrict__ pvz,
-                                                  const double* __restrict__ pm,
-                                                  const int* __restrict__ active,
-                                                  double* __restrict__ part) {
+__global__ __launch_bounds__(kBlock) void k_force(Dev d, Consts c) {
+  const Sched* __restrict__ sc = d.sc;
   if (sc->done) return;
   const int n_act = sc->n_act;
   if (n_act <= 0) return;
+  const int n = c.n;
   const Plan p = make_plan(n_act, n);
   if ((int)blockIdx.x >= p.items) return;
+  const double eps2 = c.eps2;
+  const double* __restrict__ px = d.px;
+  const double* __restrict__ py = d.py;
+  const double* __restrict__ pz = d.pz;
+  const double* __restrict__ pvx = d.pvx;
+  const double* __restrict__ pvy = d.pvy;
+  const double* __restrict__ pvz = d.pvz;
+  const double* __restrict__ pm = d.m;
+  double* __restrict__ part = d.part;
 
   __shared__ double sj[7][kTileJ];
   const int tid = threadIdx.x;
@@ -120,14 +145,16 @@ __global__ __launch_bounds__(kBlock) void k_force(const Sched* __restrict__ sc, 
 #pragma unroll
     for (int q = 0; q < kIPerLane; ++q) {
       pos[q] = itile * p.it + ilane + q * ilanes;
-      const int i = active[min(pos[q], n_act - 1)];
-      gi[q] = i;
-      xi[q] = px[i];
-      yi[q] = py[i];
-      zi[q] = pz[i];
-      vxi[q] = pvx[i];
-      vyi[q] = pvy[i];
-      vzi[q] = pvz[i];
+      // The predicted state of the active list is stored by list position
+      // (one load level instead of an index gather).
+      const int k = min(pos[q], n_act - 1);
+      gi[q] = kMaskSelf ? d.active[k] : 0;
+      xi[q] = d.ix[k];
+      yi[q] = d.iy[k];
+      zi[q] = d.iz[k];
+      vxi[q] = d.ivx[k];
+      vyi[q] = d.ivy[k];
+      vzi[q] = d.ivz[k];
       A[q] = Acc6{0, 0, 0, 0, 0, 0};
     }
 
@@ -204,36 +231,222 @@ __global__ __launch_bounds__(kBlock) void k_force(const Sched* __restrict__ sc, 
   }
 }
 
-// Sum of the slice partials of active position k, slices in ascending order.
-__device__ __forceinline__ void sum_partials(const double* __restrict__ part, int s, int n_act,
-                                             int k, double f[6]) {
+// ---------------------------------------------------------------------------
+// Slice reduction and per-particle finishing
+// ---------------------------------------------------------------------------
+
+// The s slice partials of active position k, summed by the L consecutive
+// lanes of a group (lane r takes slices r, r + L, ...) and combined by a
+// fixed xor butterfly: every lane of the group ends with the total. One
+// memory round trip instead of s dependent ones. All lanes of the wave must
+// call it (valid == false contributes zeros).
+__device__ __forceinline__ void reduce_slices(const double* __restrict__ part, int s, int n_act,
+                                              int k, int L, int r, bool valid, double f[6]) {
 #pragma unroll
-  for (int c = 0; c < 6; ++c) f[c] = part[(size_t)c * n_act + k];
-  for (int sl = 1; sl < s; ++sl) {
-    const double* o = part + (size_t)sl * 6 * n_act + k;
+  for (int q = 0; q < 6; ++q) f[q] = 0.0;
+  if (valid) {
+    for (int sl = r; sl < s; sl += L) {
+      const double* o = part + (size_t)sl * 6 * n_act + k;
 #pragma unroll
-    for (int c = 0; c < 6; ++c) f[c] += o[(size_t)c * n_act];
+      for (int q = 0; q < 6; ++q) f[q] += o[(size_t)q * n_act];
+    }
+  }
+  for (int off = L >> 1; off > 0; off >>= 1) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) f[q] += shfl_xor_d(f[q], off);
   }
 }
 
-// ---------------------------------------------------------------------------
-// Block time steps
-// ---------------------------------------------------------------------------
+// Workgroup-local bookkeeping, flushed to the Sched record with one atomic
+// per field and workgroup.
+struct LocalBook {
+  int hist[kMaxLevels + 1];
+  int clamp, bad;
+};
 
-// Smallest k >= 0 with dt_max / 2^k <= dtstar; kmax + 1 when even dt_min is
-// too large (the caller clamps and counts); 0 when dtstar is not a number
-// below dt_max (including +inf and NaN). With dtstar / dt_max = f 2^e,
-// f in [0.5, 1), the answer is exactly 1 - e.
-__device__ __forceinline__ int level_for(double dtstar, double dt_max, int kmax) {
-  if (!(dtstar < dt_max)) return 0;
-  if (!(dtstar > 0.0)) return kmax + 1;
-  int e;
-  (void)frexp(dtstar / dt_max, &e);
-  return min(1 - e, kmax + 1);
+__device__ __forceinline__ void book_init(LocalBook& b, int tid) {
+  if (tid <= kMaxLevels) b.hist[tid] = 0;
+  if (tid == 0) { b.clamp = 0; b.bad = 0; }
 }
 
-__device__ __forceinline__ double norm3(double a, double b, double c) {
-  return sqrt(a * a + b * b + c * c);
+__device__ __forceinline__ void book_flush(LocalBook& b, Sched* sc, int kmax, int tid) {
+  if (tid <= kmax && b.hist[tid] != 0) atomicAdd(&sc->hist[tid], b.hist[tid]);
+  if (tid == 0) {
+    if (b.clamp) atomicAdd((unsigned long long*)&sc->clamps, (unsigned long long)b.clamp);
+    if (b.bad) atomicOr(&sc->nonfinite, 1);
+  }
+}
+
+__device__ __forceinline__ bool finite6(const double f[6]) {
+  bool ok = true;
+#pragma unroll
+  for (int q = 0; q < 6; ++q) ok = ok && isfinite(f[q]);
+  return ok;
+}
+
+// ---------------------------------------------------------------------------
+// Corrector and new block step (Sec. 2.4 step 7(d); Sec. 3.2)
+// ---------------------------------------------------------------------------
+//
+// Per active particle: the summed new force (a1, j1); Hermite interpolation
+// of (a0, j0, a1, j1) over h gives the 2nd and 3rd derivatives a2, a3 at the
+// start of the step; corrected
+//   x = x_p + a2 h^4/24 + a3 h^5/120,  v = v_p + a2 h^3/6 + a3 h^4/24;
+// new step from the Aarseth criterion with the derivatives carried to the end
+// of the step, quantised to a power of two (shrink freely, grow by one level
+// only where the doubled step divides the new time, clamp at dt_min).
+// Everything the particle needs (slice partials, predicted state, a0, j0,
+// level) is read by list position in one memory round trip; L lanes per
+// particle share the slice reduction and the first lane corrects.
+__global__ __launch_bounds__(kBlock) void k_correct(Dev d, Consts c) {
+  Sched* __restrict__ sc = d.sc;
+  if (sc->done) return;
+  const int n_act = sc->n_act;
+  const long long t_next = sc->t_next;
+  const Plan p = make_plan(n_act, c.n);
+  const int L = correct_lanes(p.s);
+  const int per_wg = kBlock / L;
+  const int tid = threadIdx.x;
+  if ((int)blockIdx.x * per_wg >= n_act && blockIdx.x != 0) return;
+  __shared__ LocalBook bk;
+  book_init(bk, tid);
+  __syncthreads();
+  if (blockIdx.x == 0 && tid == 0) {
+    sc->block_steps += 1;
+    sc->particle_steps += n_act;
+    sc->pairs += (long long)n_act * c.n;
+    sc->t_now = t_next;
+    sc->cnt = 0;
+  }
+  const int r = tid & (L - 1);
+  for (int base = blockIdx.x * per_wg; base < n_act; base += gridDim.x * per_wg) {
+    const int k = base + tid / L;
+    const bool valid = k < n_act;
+    const int kk = valid ? k : 0;
+    // Loads that do not depend on the reduction, issued with it.
+    const int i = d.active[kk];
+    const int lv = d.ilev[kk];
+    const double a0[3] = {d.iax[kk], d.iay[kk], d.iaz[kk]};
+    const double j0[3] = {d.ijx[kk], d.ijy[kk], d.ijz[kk]};
+    const double xp[3] = {d.ix[kk], d.iy[kk], d.iz[kk]};
+    const double vp[3] = {d.ivx[kk], d.ivy[kk], d.ivz[kk]};
+    double f[6];
+    reduce_slices(d.part, p.s, n_act, k, L, r, valid, f);
+    if (r != 0 || !valid) continue;
+    if (!finite6(f)) bk.bad = 1;
+
+    const double h = (double)(1LL << (c.kmax - lv)) * c.dt_min;
+    const double h2 = h * h, h3 = h2 * h;
+    double a2[3], a3[3], a2e[3], xn[3], vn[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const double da = a0[q] - f[q];
+      a2[q] = (-6.0 * da - h * (4.0 * j0[q] + 2.0 * f[3 + q])) / h2;
+      a3[q] = (12.0 * da + 6.0 * h * (j0[q] + f[3 + q])) / h3;
+      xn[q] = xp[q] + a2[q] * (h2 * h2) / 24.0 + a3[q] * (h2 * h3) / 120.0;
+      vn[q] = vp[q] + a2[q] * h3 / 6.0 + a3[q] * (h2 * h2) / 24.0;
+      a2e[q] = a2[q] + h * a3[q];
+    }
+    const double na1 = norm3(f[0], f[1], f[2]);
+    const double nj1 = norm3(f[3], f[4], f[5]);
+    const double na2 = norm3(a2e[0], a2e[1], a2e[2]);
+    const double na3 = norm3(a3[0], a3[1], a3[2]);
+    const double dtstar = sqrt(c.eta * (na1 * na2 + nj1 * nj1) / (nj1 * na3 + na2 * na2));
+    const int kc = level_for(dtstar, c.dt_max, c.kmax);
+    int nl;
+    if (kc >= lv) {
+      nl = kc;
+    } else if (lv >= 1 && (t_next & ((1LL << (c.kmax - lv + 1)) - 1)) == 0) {
+      nl = lv - 1;
+    } else {
+      nl = lv;
+    }
+    if (nl > c.kmax) {
+      nl = c.kmax;
+      atomicAdd(&bk.clamp, 1);
+    }
+    d.x[i] = xn[0]; d.y[i] = xn[1]; d.z[i] = xn[2];
+    d.vx[i] = vn[0]; d.vy[i] = vn[1]; d.vz[i] = vn[2];
+    d.ax[i] = f[0]; d.ay[i] = f[1]; d.az[i] = f[2];
+    d.jx[i] = f[3]; d.jy[i] = f[4]; d.jz[i] = f[5];
+    d.tick[i] = t_next;
+    d.lev[i] = nl;
+    if (nl != lv) {
+      atomicAdd(&bk.hist[lv], -1);
+      atomicAdd(&bk.hist[nl], 1);
+    }
+  }
+  __syncthreads();
+  book_flush(bk, sc, c.kmax, tid);
+}
+
+// Initial block steps (Sec. 2.4 step 3; Sec. 3.2: the same eta from the
+// initial calculation on): dt* = eta |a| / |jerk|, quantised to the largest
+// dt_max / 2^k <= dt*, clamped at dt_min. Stores a, jerk, t_i = t_now and the
+// level histogram (zeroed beforehand).
+__global__ __launch_bounds__(kBlock) void k_init_dt(Dev d, Consts c) {
+  Sched* __restrict__ sc = d.sc;
+  const int n_act = sc->n_act;
+  const long long t_now = sc->t_now;
+  const Plan p = make_plan(n_act, c.n);
+  const int L = correct_lanes(p.s);
+  const int per_wg = kBlock / L;
+  const int tid = threadIdx.x;
+  __shared__ LocalBook bk;
+  book_init(bk, tid);
+  __syncthreads();
+  const int r = tid & (L - 1);
+  for (int base = blockIdx.x * per_wg; base < n_act; base += gridDim.x * per_wg) {
+    const int k = base + tid / L;
+    const bool valid = k < n_act;
+    const int i = d.active[valid ? k : 0];
+    double f[6];
+    reduce_slices(d.part, p.s, n_act, k, L, r, valid, f);
+    if (r != 0 || !valid) continue;
+    if (!finite6(f)) bk.bad = 1;
+    const double dtstar = c.eta * norm3(f[0], f[1], f[2]) / norm3(f[3], f[4], f[5]);
+    int nl = level_for(dtstar, c.dt_max, c.kmax);
+    if (nl > c.kmax) {
+      nl = c.kmax;
+      atomicAdd(&bk.clamp, 1);
+    }
+    d.ax[i] = f[0]; d.ay[i] = f[1]; d.az[i] = f[2];
+    d.jx[i] = f[3]; d.jy[i] = f[4]; d.jz[i] = f[5];
+    d.tick[i] = t_now;
+    d.lev[i] = nl;
+    atomicAdd(&bk.hist[nl], 1);
+  }
+  __syncthreads();
+  book_flush(bk, sc, c.kmax, tid);
+}
+
+// Summed forces of the current active list as (n_act, 3) row-major arrays
+// (gd_force outputs; either may be null).
+__global__ __launch_bounds__(kBlock) void k_reduce_out(Dev d, Consts c, double* __restrict__ acc,
+                                                       double* __restrict__ jerk) {
+  Sched* __restrict__ sc = d.sc;
+  const int n_act = sc->n_act;
+  const Plan p = make_plan(n_act, c.n);
+  const int L = correct_lanes(p.s);
+  const int per_wg = kBlock / L;
+  const int tid = threadIdx.x;
+  const int r = tid & (L - 1);
+  bool bad = false;
+  for (int base = blockIdx.x * per_wg; base < n_act; base += gridDim.x * per_wg) {
+    const int k = base + tid / L;
+    const bool valid = k < n_act;
+    double f[6];
+    reduce_slices(d.part, p.s, n_act, k, L, r, valid, f);
+    if (r != 0 || !valid) continue;
+    if (!finite6(f)) bad = true;
+    if (acc) {
+      acc[3 * k] = f[0]; acc[3 * k + 1] = f[1]; acc[3 * k + 2] = f[2];
+    }
+    if (jerk) {
+      jerk[3 * k] = f[3]; jerk[3 * k + 1] = f[4]; jerk[3 * k + 2] = f[5];
+    }
+  }
+  if (bad) atomicOr(&sc->nonfinite, 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -245,12 +458,15 @@ __device__ __forceinline__ double norm3(double a, double b, double c) {
 // the earliest next time is the next multiple of the smallest step present,
 // and the active set is every particle whose step divides that time, i.e.
 // level >= kmax - ctz(t_next). No O(N) search is needed for the time, and the
-// block size is the histogram's tail sum.
+// block size is the histogram's tail sum. The histogram and the clock are
+// read by parallel lanes in one memory round trip.
 //
 // Then each lane predicts one particle to t_next (Taylor series through the
 // jerk, Delta = t_next - t_j) into the j stream, and active particles are
 // appended to the active list (wave ballot + one atomic per workgroup; the
-// list order is not deterministic, but no result depends on it).
+// list order is not deterministic, but no result depends on it), together
+// with their predicted state (for the force kernel) and their a, jerk and
+// level (for the corrector), stored by list position.
 __global__ __launch_bounds__(kBlock) void k_predict(Sched* __restrict__ sc, int n, int kmax,
                                                     double dt_min, int mode, double t_explicit,
                                                     const double* __restrict__ x,
@@ -272,30 +488,57 @@ __global__ __launch_bounds__(kBlock) void k_predict(Sched* __restrict__ sc, int 
                                                     double* __restrict__ pvx,
                                                     double* __restrict__ pvy,
                                                     double* __restrict__ pvz,
-                                                    int* __restrict__ active) {
-  __shared__ long long s_tnext;
+                                                    int* __restrict__ active,
+                                                    double* __restrict__ ix, double* __restrict__ iy,
+                                                    double* __restrict__ iz,
+                                                    double* __restrict__ ivx,
+                                                    double* __restrict__ ivy,
+                                                    double* __restrict__ ivz,
+                                                    double* __restrict__ iax,
+                                                    double* __restrict__ iay,
+                                                    double* __restrict__ iaz,
+                                                    double* __restrict__ ijx,
+                                                    double* __restrict__ ijy,
+                                                    double* __restrict__ ijz,
+                                                    int* __restrict__ ilev) {
+  __shared__ long long s_tnow, s_tend, s_tnext;
+  __shared__ int s_hist[kMaxLevels + 1];
   __shared__ int s_kthr, s_done, s_base;
   __shared__ int s_wcount[kBlock / 64];
   const int tid = threadIdx.x;
+  const int j = blockIdx.x * kBlock + tid;
+  // The particle's state does not depend on the schedule: its loads are
+  // issued first and overlap the read of the histogram and the clock.
+  const int jj = min(j, n - 1);
+  const double x0 = x[jj], y0 = y[jj], z0 = z[jj];
+  const double v_x = vx[jj], v_y = vy[jj], v_z = vz[jj];
+  const double a_x = ax[jj], a_y = ay[jj], a_z = az[jj];
+  const double j_x = jx[jj], j_y = jy[jj], j_z = jz[jj];
+  const long long tj = tick[jj];
+  const int lj = lev[jj];
+  if (tid <= kmax) s_hist[tid] = sc->hist[tid];
+  if (tid == 64) s_tnow = sc->t_now;
+  if (tid == 65) s_tend = sc->t_end;
+  __syncthreads();
   if (tid == 0) {
     long long t_next;
     int kthr, nact = 0, done = 0;
     if (mode == kPredAuto) {
       int kmx = 0;
       for (int k = kmax; k >= 0; --k)
-        if (sc->hist[k] > 0) { kmx = k; break; }
+        if (s_hist[k] > 0) { kmx = k; break; }
       const long long step = 1LL << (kmax - kmx);
-      t_next = (sc->t_now / step + 1) * step;
+      t_next = (s_tnow / step + 1) * step;
       const int tz = __builtin_ctzll((unsigned long long)t_next);
       kthr = max(0, kmax - tz);
-      for (int k = kthr; k <= kmax; ++k) nact += sc->hist[k];
-      done = t_next > sc->t_end;
+      for (int k = kthr; k <= kmax; ++k) nact += s_hist[k];
+      done = t_next > s_tend;
     } else if (mode == kPredAll) {
-      t_next = sc->t_now;
+      t_next = s_tnow;
       kthr = 0;
       nact = n;
     } else {
-      t_next = sc->t_now;
+      t_next = s_tnow;
       kthr = kmax + 1;  // nobody active
     }
     s_tnext = t_next;
@@ -311,23 +554,22 @@ __global__ __launch_bounds__(kBlock) void k_predict(Sched* __restrict__ sc, int 
   __syncthreads();
   if (s_done) return;
 
-  const int j = blockIdx.x * kBlock + tid;
   bool act = false;
+  double o[6];
   if (j < n) {
-    const double dt = (mode == kPredExplicit) ? t_explicit - (double)tick[j] * dt_min
-                                              : (double)(s_tnext - tick[j]) * dt_min;
-    const double a_x = ax[j], a_y = ay[j], a_z = az[j];
-    const double j_x = jx[j], j_y = jy[j], j_z = jz[j];
-    const double v_x = vx[j], v_y = vy[j], v_z = vz[j];
+    const double dt = (mode == kPredExplicit) ? t_explicit - (double)tj * dt_min
+                                              : (double)(s_tnext - tj) * dt_min;
     const double h2 = 0.5 * dt, h3 = dt * (1.0 / 3.0);
     // x + dt (v + dt/2 (a + dt/3 jerk)),  v + dt (a + dt/2 jerk)
-    px[j] = fma(dt, fma(h2, fma(h3, j_x, a_x), v_x), x[j]);
-    py[j] = fma(dt, fma(h2, fma(h3, j_y, a_y), v_y), y[j]);
-    pz[j] = fma(dt, fma(h2, fma(h3, j_z, a_z), v_z), z[j]);
-    pvx[j] = fma(dt, fma(h2, j_x, a_x), v_x);
-    pvy[j] = fma(dt, fma(h2, j_y, a_y), v_y);
-    pvz[j] = fma(dt, fma(h2, j_z, a_z), v_z);
-    act = lev[j] >= s_kthr;
+    o[0] = fma(dt, fma(h2, fma(h3, j_x, a_x), v_x), x0);
+    o[1] = fma(dt, fma(h2, fma(h3, j_y, a_y), v_y), y0);
+    o[2] = fma(dt, fma(h2, fma(h3, j_z, a_z), v_z), z0);
+    o[3] = fma(dt, fma(h2, j_x, a_x), v_x);
+    o[4] = fma(dt, fma(h2, j_y, a_y), v_y);
+    o[5] = fma(dt, fma(h2, j_z, a_z), v_z);
+    px[j] = o[0]; py[j] = o[1]; pz[j] = o[2];
+    pvx[j] = o[3]; pvy[j] = o[4]; pvz[j] = o[5];
+    act = lj >= s_kthr;
   }
   // Workgroup compaction of the active flags.
   const unsigned long long ball = __ballot(act);
@@ -345,174 +587,14 @@ __global__ __launch_bounds__(kBlock) void k_predict(Sched* __restrict__ sc, int 
     s_base = tot ? atomicAdd(&sc->cnt, tot) : 0;
   }
   __syncthreads();
-  if (act) active[s_base + s_wcount[wave] + before] = j;
-}
-
-// ---------------------------------------------------------------------------
-// Corrector and new block step (Sec. 2.4 step 7(d); Sec. 3.2)
-// ---------------------------------------------------------------------------
-//
-// Per active particle: sum the slice partials of the new force (a1, j1);
-// Hermite interpolation of (a0, j0, a1, j1) over h gives the 2nd and 3rd
-// derivatives a2, a3 at the start of the step; corrected
-//   x = x_p + a2 h^4/24 + a3 h^5/120,  v = v_p + a2 h^3/6 + a3 h^4/24;
-// new step from the Aarseth criterion with the derivatives carried to the end
-// of the step, quantised to a power of two (shrink freely, grow by one level
-// only where the doubled step divides the new time, clamp at dt_min).
-__global__ __launch_bounds__(kBlock) void k_correct(Sched* __restrict__ sc, int n, int kmax,
-                                                    double dt_min, double dt_max, double eta,
-                                                    double* __restrict__ x, double* __restrict__ y,
-                                                    double* __restrict__ z,
-                                                    double* __restrict__ vx,
-                                                    double* __restrict__ vy,
-                                                    double* __restrict__ vz,
-                                                    double* __restrict__ ax,
-                                                    double* __restrict__ ay,
-                                                    double* __restrict__ az,
-                                                    double* __restrict__ jx,
-                                                    double* __restrict__ jy,
-                                                    double* __restrict__ jz,
-                                                    long long* __restrict__ tick,
-                                                    int* __restrict__ lev,
-                                                    const double* __restrict__ px,
-                                                    const double* __restrict__ py,
-                                                    const double* __restrict__ pz,
-                                                    const double* __restrict__ pvx,
-                                                    const double* __restrict__ pvy,
-                                                    const double* __restrict__ pvz,
-                                                    const int* __restrict__ active,
-                                                    const double* __restrict__ part) {
-  if (sc->done) return;
-  const int n_act = sc->n_act;
-  const long long t_next = sc->t_next;
-  const Plan p = make_plan(n_act, n);
-  __shared__ int lhist[kMaxLevels + 1];
-  __shared__ int lclamp, lbad;
-  const int tid = threadIdx.x;
-  if (tid <= kMaxLevels) lhist[tid] = 0;
-  if (tid == 0) { lclamp = 0; lbad = 0; }
-  __syncthreads();
-
-  for (int k = blockIdx.x * kBlock + tid; k < n_act; k += gridDim.x * kBlock) {
-    const int i = active[k];
-    double f[6];
-    sum_partials(part, p.s, n_act, k, f);
-    bool finite = true;
-#pragma unroll
-    for (int c = 0; c < 6; ++c) finite = finite && isfinite(f[c]);
-    if (!finite) lbad = 1;
-
-    const int lv = lev[i];
-    const double h = (double)(1LL << (kmax - lv)) * dt_min;
-    const double h2 = h * h, h3 = h2 * h;
-    const double a0[3] = {ax[i], ay[i], az[i]};
-    const double j0[3] = {jx[i], jy[i], jz[i]};
-    const double xp[3] = {px[i], py[i], pz[i]};
-    const double vp[3] = {pvx[i], pvy[i], pvz[i]};
-    double a2[3], a3[3], a2e[3], xn[3], vn[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const double da = a0[d] - f[d];
-      a2[d] = (-6.0 * da - h * (4.0 * j0[d] + 2.0 * f[3 + d])) / h2;
-      a3[d] = (12.0 * da + 6.0 * h * (j0[d] + f[3 + d])) / h3;
-      xn[d] = xp[d] + a2[d] * (h2 * h2) / 24.0 + a3[d] * (h2 * h3) / 120.0;
-      vn[d] = vp[d] + a2[d] * h3 / 6.0 + a3[d] * (h2 * h2) / 24.0;
-      a2e[d] = a2[d] + h * a3[d];
-    }
-    const double na1 = norm3(f[0], f[1], f[2]);
-    const double nj1 = norm3(f[3], f[4], f[5]);
-    const double na2 = norm3(a2e[0], a2e[1], a2e[2]);
-    const double na3 = norm3(a3[0], a3[1], a3[2]);
-    const double dtstar = sqrt(eta * (na1 * na2 + nj1 * nj1) / (nj1 * na3 + na2 * na2));
-
-    const int kc = level_for(dtstar, dt_max, kmax);
-    int nl;
-    if (kc >= lv) {
-      nl = kc;
-    } else if (lv >= 1 && (t_next & ((1LL << (kmax - lv + 1)) - 1)) == 0) {
-      nl = lv - 1;
-    } else {
-      nl = lv;
-    }
-    if (nl > kmax) {
-      nl = kmax;
-      atomicAdd(&lclamp, 1);
-    }
-    x[i] = xn[0]; y[i] = xn[1]; z[i] = xn[2];
-    vx[i] = vn[0]; vy[i] = vn[1]; vz[i] = vn[2];
-    ax[i] = f[0]; ay[i] = f[1]; az[i] = f[2];
-    jx[i] = f[3]; jy[i] = f[4]; jz[i] = f[5];
-    tick[i] = t_next;
-    lev[i] = nl;
-    if (nl != lv) {
-      atomicAdd(&lhist[lv], -1);
-      atomicAdd(&lhist[nl], 1);
-    }
-  }
-  __syncthreads();
-  if (tid <= kmax && lhist[tid] != 0) atomicAdd(&sc->hist[tid], lhist[tid]);
-  if (tid == 0) {
-    if (lclamp) atomicAdd((unsigned long long*)&sc->clamps, (unsigned long long)lclamp);
-    if (lbad) atomicOr(&sc->nonfinite, 1);
-    if (blockIdx.x == 0) {
-      sc->block_steps += 1;
-      sc->particle_steps += n_act;
-      sc->pairs += (long long)n_act * n;
-      sc->t_now = t_next;
-      sc->cnt = 0;
-    }
-  }
-}
-
-// Initial block steps (Sec. 2.4 step 3; Sec. 3.2: the same eta from the
-// initial calculation on): dt* = eta |a| / |jerk|, quantised to the largest
-// dt_max / 2^k <= dt*, clamped at dt_min. Also stores a, jerk, t_i = t_now
-// and the level histogram (zeroed beforehand).
-__global__ __launch_bounds__(kBlock) void k_init_dt(Sched* __restrict__ sc, int n, int kmax,
-                                                    double dt_max, double eta,
-                                                    double* __restrict__ ax,
-                                                    double* __restrict__ ay,
-                                                    double* __restrict__ az,
-                                                    double* __restrict__ jx,
-                                                    double* __restrict__ jy,
-                                                    double* __restrict__ jz,
-                                                    long long* __restrict__ tick,
-                                                    int* __restrict__ lev,
-                                                    const int* __restrict__ active,
-                                                    const double* __restrict__ part) {
-  const int n_act = sc->n_act;
-  const Plan p = make_plan(n_act, n);
-  __shared__ int lhist[kMaxLevels + 1];
-  __shared__ int lclamp, lbad;
-  const int tid = threadIdx.x;
-  if (tid <= kMaxLevels) lhist[tid] = 0;
-  if (tid == 0) { lclamp = 0; lbad = 0; }
-  __syncthreads();
-  for (int k = blockIdx.x * kBlock + tid; k < n_act; k += gridDim.x * kBlock) {
-    const int i = active[k];
-    double f[6];
-    sum_partials(part, p.s, n_act, k, f);
-    bool finite = true;
-#pragma unroll
-    for (int c = 0; c < 6; ++c) finite = finite && isfinite(f[c]);
-    if (!finite) lbad = 1;
-    const double dtstar = eta * norm3(f[0], f[1], f[2]) / norm3(f[3], f[4], f[5]);
-    int nl = level_for(dtstar, dt_max, kmax);
-    if (nl > kmax) {
-      nl = kmax;
-      atomicAdd(&lclamp, 1);
-    }
-    ax[i] = f[0]; ay[i] = f[1]; az[i] = f[2];
-    jx[i] = f[3]; jy[i] = f[4]; jz[i] = f[5];
-    tick[i] = sc->t_now;
-    lev[i] = nl;
-    atomicAdd(&lhist[nl], 1);
-  }
-  __syncthreads();
-  if (tid <= kmax && lhist[tid] != 0) atomicAdd(&sc->hist[tid], lhist[tid]);
-  if (tid == 0) {
-    if (lclamp) atomicAdd((unsigned long long*)&sc->clamps, (unsigned long long)lclamp);
-    if (lbad) atomicOr(&sc->nonfinite, 1);
+  if (act) {
+    const int k = s_base + s_wcount[wave] + before;
+    active[k] = j;
+    ix[k] = o[0]; iy[k] = o[1]; iz[k] = o[2];
+    ivx[k] = o[3]; ivy[k] = o[4]; ivz[k] = o[5];
+    iax[k] = a_x; iay[k] = a_y; iaz[k] = a_z;
+    ijx[k] = j_x; ijy[k] = j_y; ijz[k] = j_z;
+    ilev[k] = lj;
   }
 }
 
@@ -683,7 +765,13 @@ __global__ void k_set_tend(Sched* __restrict__ sc, long long t_end) {
 
 // Explicit active list for gd_force(idx, ...): range-checked copy.
 __global__ void k_set_active(Sched* __restrict__ sc, int n, const int32_t* __restrict__ idx,
-                             int n_act, int* __restrict__ active) {
+                             int n_act, int* __restrict__ active, const double* __restrict__ px,
+                             const double* __restrict__ py, const double* __restrict__ pz,
+                             const double* __restrict__ pvx, const double* __restrict__ pvy,
+                             const double* __restrict__ pvz, double* __restrict__ ix,
+                             double* __restrict__ iy, double* __restrict__ iz,
+                             double* __restrict__ ivx, double* __restrict__ ivy,
+                             double* __restrict__ ivz) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k == 0) {
     sc->n_act = n_act;
@@ -696,23 +784,8 @@ __global__ void k_set_active(Sched* __restrict__ sc, int n, const int32_t* __res
     i = 0;
   }
   active[k] = i;
-}
-
-// Forces of the current active list as (n_act, 3) row-major arrays.
-__global__ void k_gather_forces(const Sched* __restrict__ sc, int n, const double* __restrict__ part,
-                                double* __restrict__ acc, double* __restrict__ jerk) {
-  const int n_act = sc->n_act;
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n_act) return;
-  const Plan p = make_plan(n_act, n);
-  double f[6];
-  sum_partials(part, p.s, n_act, k, f);
-  if (acc) {
-    acc[3 * k] = f[0]; acc[3 * k + 1] = f[1]; acc[3 * k + 2] = f[2];
-  }
-  if (jerk) {
-    jerk[3 * k] = f[3]; jerk[3 * k + 1] = f[4]; jerk[3 * k + 2] = f[5];
-  }
+  ix[k] = px[i]; iy[k] = py[i]; iz[k] = pz[i];
+  ivx[k] = pvx[i]; ivy[k] = pvy[i]; ivz[k] = pvz[i];
 }
 
 __global__ void k_copy_active(const Sched* __restrict__ sc, const int* __restrict__ active,
@@ -802,33 +875,36 @@ hipError_t launch_predict(const Dev& d, const Consts& c, int mode, double t_expl
   hipLaunchKernelGGL(k_predict, dim3(grid_for(c.n)), dim3(kBlock), 0, s, d.sc, c.n, c.kmax,
                      c.dt_min, mode, t_explicit, d.x, d.y, d.z, d.vx, d.vy, d.vz, d.ax, d.ay,
                      d.az, d.jx, d.jy, d.jz, d.tick, d.lev, d.px, d.py, d.pz, d.pvx, d.pvy,
-                     d.pvz, d.active);
+                     d.pvz, d.active, d.ix, d.iy, d.iz, d.ivx, d.ivy, d.ivz, d.iax, d.iay, d.iaz,
+                     d.ijx, d.ijy, d.ijz, d.ilev);
   return hipGetLastError();
 }
 
-hipError_t launch_force(const Dev& d, const Consts& c, hipStream_t s) {
-  if (c.eps2 > 0.0) {
-    hipLaunchKernelGGL(k_force<false>, dim3(kForceGrid), dim3(kBlock), 0, s, d.sc, c.n, c.eps2,
-                       d.px, d.py, d.pz, d.pvx, d.pvy, d.pvz, d.m, d.active, d.part);
+hipError_t launch_force(const Dev& d, const Consts& c, hipStream_t s, hipEvent_t ev_start,
+                        hipEvent_t ev_stop) {
+  auto kern = c.eps2 > 0.0 ? k_force<false> : k_force<true>;
+  if (ev_start) {
+    // The events take the dispatch's own start and end timestamps.
+    hipExtLaunchKernelGGL(kern, dim3(c.force_grid), dim3(kBlock), 0, s, ev_start, ev_stop, 0, d, c);
   } else {
-    hipLaunchKernelGGL(k_force<true>, dim3(kForceGrid), dim3(kBlock), 0, s, d.sc, c.n, c.eps2,
-                       d.px, d.py, d.pz, d.pvx, d.pvy, d.pvz, d.m, d.active, d.part);
+    hipLaunchKernelGGL(kern, dim3(c.force_grid), dim3(kBlock), 0, s, d, c);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_correct(const Dev& d, const Consts& c, hipStream_t s) {
-  hipLaunchKernelGGL(k_correct, dim3(grid_for(c.n)), dim3(kBlock), 0, s, d.sc, c.n, c.kmax,
-                     c.dt_min, c.dt_max, c.eta, d.x, d.y, d.z, d.vx, d.vy, d.vz, d.ax, d.ay,
-                     d.az, d.jx, d.jy, d.jz, d.tick, d.lev, d.px, d.py, d.pz, d.pvx, d.pvy,
-                     d.pvz, d.active, d.part);
+  hipLaunchKernelGGL(k_correct, dim3(c.correct_grid), dim3(kBlock), 0, s, d, c);
   return hipGetLastError();
 }
 
 hipError_t launch_init_dt(const Dev& d, const Consts& c, hipStream_t s) {
-  hipLaunchKernelGGL(k_init_dt, dim3(grid_for(c.n)), dim3(kBlock), 0, s, d.sc, c.n, c.kmax,
-                     c.dt_max, c.eta, d.ax, d.ay, d.az, d.jx, d.jy, d.jz, d.tick, d.lev,
-                     d.active, d.part);
+  hipLaunchKernelGGL(k_init_dt, dim3(c.correct_grid), dim3(kBlock), 0, s, d, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_out(const Dev& d, const Consts& c, double* acc, double* jerk,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_out, dim3(c.correct_grid), dim3(kBlock), 0, s, d, c, acc, jerk);
   return hipGetLastError();
 }
 
@@ -856,14 +932,8 @@ hipError_t launch_reset_sched(const Dev& d, long long t_now, hipStream_t s) {
 hipError_t launch_set_active(const Dev& d, const Consts& c, const int32_t* idx, int n_act,
                              hipStream_t s) {
   hipLaunchKernelGGL(k_set_active, dim3(grid_for(n_act > 0 ? n_act : 1)), dim3(kBlock), 0, s,
-                     d.sc, c.n, idx, n_act, d.active);
-  return hipGetLastError();
-}
-
-hipError_t launch_gather_forces(const Dev& d, const Consts& c, int n_rows_max, double* acc,
-                                double* jerk, hipStream_t s) {
-  hipLaunchKernelGGL(k_gather_forces, dim3(grid_for(n_rows_max)), dim3(kBlock), 0, s, d.sc, c.n,
-                     d.part, acc, jerk);
+                     d.sc, c.n, idx, n_act, d.active, d.px, d.py, d.pz, d.pvx, d.pvy, d.pvz, d.ix,
+                     d.iy, d.iz, d.ivx, d.ivy, d.ivz);
   return hipGetLastError();
 }
 

@@ -59,6 +59,9 @@ def library():
     i64, st = C.c_int64, C.c_int
     lib.gd_workspace_bytes.argtypes = [i64, C.POINTER(gd_params), C.POINTER(C.c_size_t)]
     lib.gd_init.argtypes = [C.POINTER(_VP), C.POINTER(gd_params), i64, _VP, _VP, _VP, _VP, C.c_size_t, _VP]
+    lib.gd_reinit.argtypes = [_VP, _VP, _VP, _VP]
+    lib.gd_profile_force.argtypes = [_VP, C.c_int]
+    lib.gd_profile_get.argtypes = [_VP, C.POINTER(C.c_double), C.POINTER(i64), C.POINTER(i64)]
     lib.gd_predict.argtypes = [_VP, C.POINTER(C.c_double)]
     lib.gd_force.argtypes = [_VP, _VP, i64, _VP, _VP]
     lib.gd_active.argtypes = [_VP, _VP, C.POINTER(i64)]
@@ -68,7 +71,7 @@ def library():
     lib.gd_get_state.argtypes = [_VP, _VP, _VP, _VP, _VP, _VP, _VP, C.POINTER(C.c_double)]
     lib.gd_set_state.argtypes = [_VP, _VP, _VP, _VP, _VP, _VP, _VP, C.c_double]
     lib.gd_stats_get.argtypes = [_VP, C.POINTER(gd_stats)]
-    for name in ["gd_workspace_bytes", "gd_init", "gd_predict", "gd_force", "gd_active", "gd_correct",
+    for name in ["gd_workspace_bytes", "gd_init", "gd_reinit", "gd_profile_force", "gd_profile_get", "gd_predict", "gd_force", "gd_active", "gd_correct",
                  "gd_step_to", "gd_energy", "gd_get_state", "gd_set_state", "gd_stats_get"]:
         getattr(lib, name).restype = st
     lib.gd_destroy.argtypes = [_VP]
@@ -126,6 +129,22 @@ def gd_init(params: gd_params, m, x, v, workspace, stream=None):
                            _stream_handle(stream))
     _check(rc, None)
     return ctx
+
+
+def gd_reinit(ctx, m, x, v) -> None:
+    n = m.shape[0]
+    _check(library().gd_reinit(ctx, _ptr(m, torch.float64, (n,), "m"), _ptr(x, torch.float64, (n, 3), "x"),
+                               _ptr(v, torch.float64, (n, 3), "v")), ctx)
+
+
+def gd_profile_force(ctx, enable: bool = True) -> None:
+    _check(library().gd_profile_force(ctx, int(bool(enable))), ctx)
+
+
+def gd_profile_get(ctx) -> dict:
+    ms, launches, pairs = C.c_double(), C.c_int64(), C.c_int64()
+    _check(library().gd_profile_get(ctx, C.byref(ms), C.byref(launches), C.byref(pairs)), ctx)
+    return {"force_ms": ms.value, "launches": int(launches.value), "pairs": int(pairs.value)}
 
 
 def gd_predict(ctx, t: float | None = None) -> None:

@@ -234,3 +234,30 @@ def test_error_paths():
     assert st["t"] == 0.125
     g.gd_energy(cl.ctx)
     cl.close()
+
+
+def test_reinit_matches_init_and_profiles_force():
+    """gd_reinit on a used context equals a fresh gd_init bitwise; force
+    timing counts the initial launch and the block steps' launches, and the
+    timed (direct-launch) run gives the same state as the graph replay."""
+    n = 1024
+    m, x, v = plummer(n, 7)
+    a = g.Cluster(m, x, v, eta=ETA, eps=EPS, device=DEV)
+    g.gd_step_to(a.ctx, 0.25)
+    g.gd_profile_force(a.ctx, True)
+    g.gd_reinit(a.ctx, dev(m), dev(x), dev(v))
+    st0 = g.gd_stats_get(a.ctx)
+    assert st0["block_steps"] == 0 and st0["t"] == 0.0
+    b = g.Cluster(m, x, v, eta=ETA, eps=EPS, device=DEV)
+    for u, w in zip(a.state()[:6], b.state()[:6]):
+        np.testing.assert_array_equal(host(u), host(w))
+    st = g.gd_step_to(a.ctx, 0.125)
+    prof = g.gd_profile_get(a.ctx)
+    assert prof["launches"] == st["block_steps"] + 1
+    assert prof["pairs"] == st["pair_interactions"] + n * n
+    assert prof["force_ms"] > 0
+    g.gd_step_to(b.ctx, 0.125)
+    for u, w in zip(a.state()[:6], b.state()[:6]):
+        np.testing.assert_array_equal(host(u), host(w))
+    a.close()
+    b.close()
