@@ -42,7 +42,38 @@ def _load():
         return _lib
     if not os.path.exists(_LIB):
         build()
-    lib = C.CDLL(_LIB)
+    _lib = _bind(C.CDLL(_LIB))
+    return _lib
+
+
+class using:
+    """Context manager: route every oracle call through another build of the
+    oracle source (e.g. a copy with a planted mistake, in the tests)."""
+
+    def __init__(self, lib_path):
+        self.path = lib_path
+
+    def __enter__(self):
+        global _lib
+        self.saved = _load()
+        _lib = _bind(C.CDLL(self.path))
+        return _lib
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self.saved
+        return False
+
+
+def compile_source(src_path, out_path):
+    """Compile an oracle source file with the same flags as build()."""
+    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+           "-fPIC", "-shared", "-o", out_path, src_path, "-lm"]
+    subprocess.run(cmd, check=True, capture_output=True)
+    return out_path
+
+
+def _bind(lib):
     i64, dbl, cint = C.c_int64, C.c_double, C.c_int
     lib.or_force.argtypes = [i64, _dp, _dp, _dp, dbl, i64, C.c_void_p, _dp, _dp, cint, cint]
     lib.or_force.restype = cint
@@ -71,7 +102,6 @@ def _load():
     lib.or_run.restype = i64
     lib.or_max_threads.argtypes = []
     lib.or_max_threads.restype = cint
-    _lib = lib
     return lib
 
 
