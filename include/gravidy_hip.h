@@ -54,11 +54,14 @@ typedef enum {
 } gd_status;
 
 typedef struct {
-  double eta;     /* time-step accuracy parameter (Sec. 3.2; paper default 0.01), > 0 */
-  double eps;     /* Plummer softening length (Eq. (3); paper default 1e-4); 0 or >= 1e-30 */
-  double dt_max;  /* largest block step, a power of two (e.g. 0.125) */
-  double dt_min;  /* smallest block step, a power of two <= dt_max (e.g. 2^-22) */
-  int32_t flags;  /* reserved, must be 0 */
+  double eta;        /* time-step accuracy parameter (Sec. 3.2; paper default 0.01), > 0 */
+  double eps;        /* Plummer softening length (Eq. (3); paper default 1e-4); 0 or >= 1e-30 */
+  double eps_bh;     /* softening of every pair that involves the central particle */
+  double dt_max;     /* largest block step, a power of two (e.g. 0.125) */
+  double dt_min;     /* smallest block step, a power of two <= dt_max (e.g. 2^-22) */
+  int64_t bh_index;  /* central massive particle (Sec. 6, planned extension), -1 for none;
+                        with one, eps and eps_bh must both be >= 1e-30 */
+  int32_t flags;     /* reserved, must be 0 */
 } gd_params;
 
 typedef struct {

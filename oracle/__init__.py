@@ -75,9 +75,9 @@ def compile_source(src_path, out_path):
 
 def _bind(lib):
     i64, dbl, cint = C.c_int64, C.c_double, C.c_int
-    lib.or_force.argtypes = [i64, _dp, _dp, _dp, dbl, i64, C.c_void_p, _dp, _dp, cint, cint]
+    lib.or_force.argtypes = [i64, _dp, _dp, _dp, dbl, dbl, i64, i64, C.c_void_p, _dp, _dp, cint, cint]
     lib.or_force.restype = cint
-    lib.or_energy.argtypes = [i64, _dp, _dp, _dp, dbl, C.POINTER(dbl), C.POINTER(dbl), C.POINTER(dbl)]
+    lib.or_energy.argtypes = [i64, _dp, _dp, _dp, dbl, dbl, i64, C.POINTER(dbl), C.POINTER(dbl), C.POINTER(dbl)]
     lib.or_energy.restype = cint
     lib.or_predict.argtypes = [i64, _dp, _dp, _dp, _dp, _dp, dbl, _dp, _dp]
     lib.or_predict.restype = None
@@ -91,13 +91,13 @@ def _bind(lib):
     lib.or_dt_aarseth.restype = dbl
     lib.or_quantize.argtypes = [dbl, dbl, dbl, dbl, dbl, C.POINTER(i64)]
     lib.or_quantize.restype = dbl
-    lib.or_init.argtypes = [i64, _dp, _dp, _dp, dbl, dbl, dbl, dbl, _dp, _dp, _dp, _dp,
+    lib.or_init.argtypes = [i64, _dp, _dp, _dp, dbl, dbl, i64, dbl, dbl, dbl, _dp, _dp, _dp, _dp,
                             C.POINTER(i64), cint]
     lib.or_init.restype = cint
-    lib.or_block_step.argtypes = [i64, _dp, _dp, _dp, _dp, _dp, _dp, _dp, dbl, dbl, dbl, dbl,
+    lib.or_block_step.argtypes = [i64, _dp, _dp, _dp, _dp, _dp, _dp, _dp, dbl, dbl, i64, dbl, dbl, dbl,
                                   C.POINTER(dbl), _ip, C.POINTER(i64), cint]
     lib.or_block_step.restype = i64
-    lib.or_run.argtypes = [i64, _dp, _dp, _dp, _dp, _dp, _dp, _dp, dbl, dbl, dbl, dbl,
+    lib.or_run.argtypes = [i64, _dp, _dp, _dp, _dp, _dp, _dp, _dp, dbl, dbl, i64, dbl, dbl, dbl,
                            C.POINTER(dbl), dbl, dbl, _ip, _dp, i64, cint]
     lib.or_run.restype = i64
     lib.or_max_threads.argtypes = []
@@ -116,9 +116,10 @@ def max_threads() -> int:
     return int(_load().or_max_threads())
 
 
-def force(m, x, v, eps, idx=None, compensated=False, threads=1):
+def force(m, x, v, eps, idx=None, compensated=False, threads=1, eps_bh=None, bh=-1):
     """Softened acceleration and jerk of particles idx (all when None) from all
-    particles. Returns (acc[n_act, 3], jerk[n_act, 3])."""
+    particles; pairs with particle bh (if >= 0) are softened with eps_bh.
+    Returns (acc[n_act, 3], jerk[n_act, 3])."""
     lib = _load()
     m = _f64(m)
     n = m.shape[0]
@@ -133,20 +134,24 @@ def force(m, x, v, eps, idx=None, compensated=False, threads=1):
         n_act, ip = keep.shape[0], keep.ctypes.data_as(C.c_void_p)
     acc = np.zeros((n_act, 3))
     jrk = np.zeros((n_act, 3))
-    rc = lib.or_force(n, m, x, v, float(eps), n_act, ip, acc, jrk, int(bool(compensated)), int(threads))
+    e_bh = float(eps if eps_bh is None else eps_bh)
+    rc = lib.or_force(n, m, x, v, float(eps), e_bh, int(bh), n_act, ip, acc, jrk, int(bool(compensated)),
+                      int(threads))
     if rc:
         raise ValueError(f"or_force failed ({rc})")
     return acc, jrk
 
 
-def energy(m, x, v, eps, unsoftened=False):
+def energy(m, x, v, eps, unsoftened=False, eps_bh=None, bh=-1):
     """(ekin, epot_softened[, epot_unsoftened]) of a synchronised state."""
     lib = _load()
     m = _f64(m)
     n = m.shape[0]
     x, v = _f64(x, (n, 3)), _f64(v, (n, 3))
     ek, ep, eu = C.c_double(), C.c_double(), C.c_double()
-    rc = lib.or_energy(n, m, x, v, float(eps), C.byref(ek), C.byref(ep), C.byref(eu) if unsoftened else None)
+    e_bh = float(eps if eps_bh is None else eps_bh)
+    rc = lib.or_energy(n, m, x, v, float(eps), e_bh, int(bh), C.byref(ek), C.byref(ep),
+                       C.byref(eu) if unsoftened else None)
     if rc:
         raise ValueError(f"or_energy failed ({rc})")
     if unsoftened:
@@ -205,7 +210,7 @@ class State:
     """Oracle integrator state: the particle arrays plus per-particle times and
     block steps (row-major (n, 3) arrays)."""
 
-    def __init__(self, m, x, v, eps, eta, dt_max, dt_min, threads=1):
+    def __init__(self, m, x, v, eps, eta, dt_max, dt_min, threads=1, eps_bh=None, bh=-1):
         if not (_is_pow2(dt_max) and _is_pow2(dt_min) and dt_min <= dt_max):
             raise ValueError("dt_max and dt_min must be powers of two with dt_min <= dt_max")
         self.m = _f64(m).copy()
@@ -216,6 +221,7 @@ class State:
         self.x = _f64(x, (n, 3)).copy()
         self.v = _f64(v, (n, 3)).copy()
         self.eps, self.eta, self.dt_max, self.dt_min = float(eps), float(eta), float(dt_max), float(dt_min)
+        self.eps_bh, self.bh = float(eps if eps_bh is None else eps_bh), int(bh)
         self.threads = int(threads)
         self.a = np.zeros((n, 3))
         self.jk = np.zeros((n, 3))
@@ -225,16 +231,17 @@ class State:
         # block steps, particle steps, pair interactions, dt_min clamps
         self.stats = np.zeros(4, dtype=np.int64)
         clamps = C.c_int64(0)
-        rc = _load().or_init(n, self.m, self.x, self.v, self.eps, self.eta, self.dt_max, self.dt_min,
-                             self.a, self.jk, self.t_i, self.dt_i, C.byref(clamps), self.threads)
+        rc = _load().or_init(n, self.m, self.x, self.v, self.eps, self.eps_bh, self.bh, self.eta, self.dt_max,
+                             self.dt_min, self.a, self.jk, self.t_i, self.dt_i, C.byref(clamps), self.threads)
         if rc:
             raise ValueError(f"or_init failed ({rc})")
         self.stats[3] += clamps.value
-        ek, ep = energy(self.m, self.x, self.v, self.eps)
+        ek, ep = energy(self.m, self.x, self.v, self.eps, eps_bh=self.eps_bh, bh=self.bh)
         self.e0 = ek + ep
 
     @classmethod
-    def from_arrays(cls, m, x, v, a, jk, t_i, dt_i, t_now, eps, eta, dt_max, dt_min, threads=1):
+    def from_arrays(cls, m, x, v, a, jk, t_i, dt_i, t_now, eps, eta, dt_max, dt_min, threads=1,
+                    eps_bh=None, bh=-1):
         """A state set from saved arrays (no initial force evaluation)."""
         self = cls.__new__(cls)
         self.m = _f64(m).copy()
@@ -244,6 +251,7 @@ class State:
         self.t_i, self.dt_i = _f64(t_i).copy(), _f64(dt_i).copy()
         self.t_now = float(t_now)
         self.eps, self.eta, self.dt_max, self.dt_min = float(eps), float(eta), float(dt_max), float(dt_min)
+        self.eps_bh, self.bh = float(eps if eps_bh is None else eps_bh), int(bh)
         self.threads = int(threads)
         self.stats = np.zeros(4, dtype=np.int64)
         self.e0 = float("nan")
@@ -255,8 +263,8 @@ class State:
         t_now = C.c_double(self.t_now)
         clamps = C.c_int64(0)
         n_act = _load().or_block_step(self.n, self.m, self.x, self.v, self.a, self.jk, self.t_i, self.dt_i,
-                                      self.eps, self.eta, self.dt_max, self.dt_min, C.byref(t_now), active,
-                                      C.byref(clamps), self.threads)
+                                      self.eps, self.eps_bh, self.bh, self.eta, self.dt_max, self.dt_min,
+                                      C.byref(t_now), active, C.byref(clamps), self.threads)
         if n_act < 0:
             raise RuntimeError(f"or_block_step failed ({n_act})")
         self.t_now = t_now.value
@@ -273,8 +281,8 @@ class State:
         t_now = C.c_double(self.t_now)
         stats = np.zeros(4, dtype=np.int64)
         nrows = _load().or_run(self.n, self.m, self.x, self.v, self.a, self.jk, self.t_i, self.dt_i,
-                               self.eps, self.eta, self.dt_max, self.dt_min, C.byref(t_now), float(t_end),
-                               float(self.e0), stats, rows, max_rows, self.threads)
+                               self.eps, self.eps_bh, self.bh, self.eta, self.dt_max, self.dt_min, C.byref(t_now),
+                               float(t_end), float(self.e0), stats, rows, max_rows, self.threads)
         if nrows < 0:
             raise RuntimeError(f"or_run failed ({nrows})")
         self.t_now = t_now.value
@@ -282,5 +290,5 @@ class State:
         return rows[:nrows].copy()
 
     def energy(self):
-        ek, ep = energy(self.m, self.x, self.v, self.eps)
+        ek, ep = energy(self.m, self.x, self.v, self.eps, eps_bh=self.eps_bh, bh=self.bh)
         return ek + ep

@@ -23,7 +23,11 @@
  *     Sec. 2.4, Sec. 3.2);
  *   - energy: the kinetic plus the softened potential, the quantity that the
  *     softened dynamics conserve (Eq. (2) prints the unsoftened one, which is
- *     also returned).
+ *     also returned);
+ *   - central massive particle (the paper's planned extension, Sec. 6): when
+ *     bh >= 0, every pair that involves particle bh is softened with eps_bh
+ *     instead of eps (symmetric, so Newton's third law still holds); bh < 0
+ *     means no such particle.
  *
  * Array conventions: positions, velocities, accelerations and jerks are
  * row-major (n, 3) double arrays; index arrays are int64.
@@ -67,6 +71,12 @@ static inline void neumaier_add(double* s, double* c, double x) {
   *s = t;
 }
 
+/* Squared softening of pair (i, j): eps_bh^2 when either is the central
+ * particle bh, eps^2 otherwise. */
+static inline double pair_eps2(int64_t i, int64_t j, double eps2, double eps2_bh, int64_t bh) {
+  return (bh >= 0 && (i == bh || j == bh)) ? eps2_bh : eps2;
+}
+
 /*
  * Softened acceleration and jerk of particle i from all j != i.
  *
@@ -78,7 +88,8 @@ static inline void neumaier_add(double* s, double* c, double x) {
  * w = v_j - v_i. The j = i term is excluded as in Eq. (1).
  */
 static void pair_sum(int64_t n, const double* m, const double* x, const double* v,
-                     double eps2, int64_t i, int compensated, double* acc, double* jrk) {
+                     double eps2, double eps2_bh, int64_t bh, int64_t i, int compensated,
+                     double* acc, double* jrk) {
   double s_acc[3] = {0, 0, 0}, c_acc[3] = {0, 0, 0};
   double s_jrk[3] = {0, 0, 0}, c_jrk[3] = {0, 0, 0};
   const double* xi = x + 3 * i;
@@ -90,7 +101,7 @@ static void pair_sum(int64_t n, const double* m, const double* x, const double* 
       r[d] = x[3 * j + d] - xi[d];
       w[d] = v[3 * j + d] - vi[d];
     }
-    double s = r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + eps2;
+    double s = r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + pair_eps2(i, j, eps2, eps2_bh, bh);
     double s32 = s * sqrt(s);
     double s52 = s32 * s;
     double rw = r[0] * w[0] + r[1] * w[1] + r[2] * w[2];
@@ -120,15 +131,16 @@ static void pair_sum(int64_t n, const double* m, const double* x, const double* 
  * a higher-accuracy reference; the plain mode is the definition itself.
  */
 int or_force(int64_t n, const double* m, const double* x, const double* v, double eps,
-             int64_t n_act, const int64_t* idx, double* acc, double* jrk,
-             int compensated, int nthreads) {
-  if (n < 1 || n_act < 0) return OR_EINVAL;
+             double eps_bh, int64_t bh, int64_t n_act, const int64_t* idx, double* acc,
+             double* jrk, int compensated, int nthreads) {
+  if (n < 1 || n_act < 0 || bh >= n) return OR_EINVAL;
   double eps2 = eps * eps;
+  double eps2_bh = eps_bh * eps_bh;
   set_threads(nthreads);
 #pragma omp parallel for schedule(dynamic, 16)
   for (int64_t k = 0; k < n_act; ++k) {
     int64_t i = idx ? idx[k] : k;
-    pair_sum(n, m, x, v, eps2, i, compensated, acc + 3 * k, jrk + 3 * k);
+    pair_sum(n, m, x, v, eps2, eps2_bh, bh, i, compensated, acc + 3 * k, jrk + 3 * k);
   }
   return OR_OK;
 }
@@ -141,9 +153,10 @@ int or_force(int64_t n, const double* m, const double* x, const double* v, doubl
  * j > i ascending); sums are compensated.
  */
 int or_energy(int64_t n, const double* m, const double* x, const double* v, double eps,
-              double* ekin, double* epot, double* epot_unsoft) {
-  if (n < 1) return OR_EINVAL;
+              double eps_bh, int64_t bh, double* ekin, double* epot, double* epot_unsoft) {
+  if (n < 1 || bh >= n) return OR_EINVAL;
   double eps2 = eps * eps;
+  double eps2_bh = eps_bh * eps_bh;
   double sk = 0, ck = 0, sp = 0, cp = 0, su = 0, cu = 0;
   for (int64_t i = 0; i < n; ++i) {
     double v2 = v[3 * i] * v[3 * i] + v[3 * i + 1] * v[3 * i + 1] + v[3 * i + 2] * v[3 * i + 2];
@@ -152,7 +165,7 @@ int or_energy(int64_t n, const double* m, const double* x, const double* v, doub
       double dx = x[3 * i] - x[3 * j], dy = x[3 * i + 1] - x[3 * j + 1], dz = x[3 * i + 2] - x[3 * j + 2];
       double r2 = dx * dx + dy * dy + dz * dz;
       double mm = m[i] * m[j];
-      neumaier_add(&sp, &cp, -mm / sqrt(r2 + eps2));
+      neumaier_add(&sp, &cp, -mm / sqrt(r2 + pair_eps2(i, j, eps2, eps2_bh, bh)));
       if (epot_unsoft) neumaier_add(&su, &cu, -mm / sqrt(r2));
     }
   }
@@ -271,10 +284,10 @@ double or_quantize(double dtstar, double dt_old, double t_new, double dt_max, do
  * Initialisation (Sec. 2.4 steps 2-3): forces of all particles at t = 0
  * (O(N^2)), t_i = 0, and the initial block step of every particle.
  */
-int or_init(int64_t n, const double* m, const double* x, const double* v, double eps, double eta,
-            double dt_max, double dt_min, double* a, double* jk, double* t_i, double* dt_i,
-            int64_t* clamps, int nthreads) {
-  int rc = or_force(n, m, x, v, eps, n, NULL, a, jk, 0, nthreads);
+int or_init(int64_t n, const double* m, const double* x, const double* v, double eps,
+            double eps_bh, int64_t bh, double eta, double dt_max, double dt_min, double* a,
+            double* jk, double* t_i, double* dt_i, int64_t* clamps, int nthreads) {
+  int rc = or_force(n, m, x, v, eps, eps_bh, bh, n, NULL, a, jk, 0, nthreads);
   if (rc) return rc;
   for (int64_t i = 0; i < n; ++i) {
     t_i[i] = 0.0;
@@ -298,9 +311,9 @@ int or_init(int64_t n, const double* m, const double* x, const double* v, double
  * (negative on error). *t_now is set to t_next.
  */
 int64_t or_block_step(int64_t n, const double* m, double* x, double* v, double* a, double* jk,
-                      double* t_i, double* dt_i, double eps, double eta, double dt_max,
-                      double dt_min, double* t_now, int64_t* active_out, int64_t* clamps,
-                      int nthreads) {
+                      double* t_i, double* dt_i, double eps, double eps_bh, int64_t bh,
+                      double eta, double dt_max, double dt_min, double* t_now,
+                      int64_t* active_out, int64_t* clamps, int nthreads) {
   double t_next = INFINITY;
   for (int64_t i = 0; i < n; ++i)
     if (t_i[i] + dt_i[i] < t_next) t_next = t_i[i] + dt_i[i];
@@ -317,7 +330,7 @@ int64_t or_block_step(int64_t n, const double* m, double* x, double* v, double* 
     return OR_ENOMEM;
   }
   or_predict(n, x, v, a, jk, t_i, t_next, xp, vp);
-  or_force(n, m, xp, vp, eps, n_act, active_out, a1, j1, 0, nthreads);
+  or_force(n, m, xp, vp, eps, eps_bh, bh, n_act, active_out, a1, j1, 0, nthreads);
   for (int64_t k = 0; k < n_act; ++k) {
     int64_t i = active_out[k];
     double h = dt_i[i];
@@ -351,16 +364,16 @@ int64_t or_block_step(int64_t n, const double* m, double* x, double* v, double* 
  * negative on error.
  */
 int64_t or_run(int64_t n, const double* m, double* x, double* v, double* a, double* jk,
-               double* t_i, double* dt_i, double eps, double eta, double dt_max, double dt_min,
-               double* t_now, double t_end, double e0, int64_t* stats, double* rows,
-               int64_t max_rows, int nthreads) {
+               double* t_i, double* dt_i, double eps, double eps_bh, int64_t bh, double eta,
+               double dt_max, double dt_min, double* t_now, double t_end, double e0,
+               int64_t* stats, double* rows, int64_t max_rows, int nthreads) {
   int64_t* active = (int64_t*)malloc(sizeof(int64_t) * n);
   if (!active) return OR_ENOMEM;
   int64_t nrows = 0;
   double e_prev = e0;
   while (*t_now < t_end) {
-    int64_t n_act = or_block_step(n, m, x, v, a, jk, t_i, dt_i, eps, eta, dt_max, dt_min, t_now,
-                                  active, &stats[3], nthreads);
+    int64_t n_act = or_block_step(n, m, x, v, a, jk, t_i, dt_i, eps, eps_bh, bh, eta, dt_max,
+                                  dt_min, t_now, active, &stats[3], nthreads);
     if (n_act < 0) {
       free(active);
       return n_act;
@@ -375,7 +388,7 @@ int64_t or_run(int64_t n, const double* m, double* x, double* v, double* a, doub
           return OR_ESTATE;
         }
       double ek, ep;
-      or_energy(n, m, x, v, eps, &ek, &ep, NULL);
+      or_energy(n, m, x, v, eps, eps_bh, bh, &ek, &ep, NULL);
       double e = ek + ep;
       if (nrows < max_rows) {
         double* r = rows + 8 * nrows;

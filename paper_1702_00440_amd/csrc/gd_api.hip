@@ -33,7 +33,7 @@ size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // Byte offsets of every array in the workspace.
 struct Layout {
-  size_t sc, m, x[3], v[3], a[3], j[3], p[3], pv[3], tick, lev, active, ip[3], ipv[3], ia[3], ij[3], ilev,
+  size_t sc, m, jm, x[3], v[3], a[3], j[3], p[3], pv[3], tick, lev, active, ip[3], ipv[3], ia[3], ij[3], ilev,
       part, ebuf, total;
 };
 
@@ -48,6 +48,7 @@ Layout make_layout(long long n) {
   const size_t nd = sizeof(double) * (size_t)n;
   L.sc = take(sizeof(Sched));
   L.m = take(nd);
+  L.jm = take(nd);
   for (int d = 0; d < 3; ++d) L.x[d] = take(nd);
   for (int d = 0; d < 3; ++d) L.v[d] = take(nd);
   for (int d = 0; d < 3; ++d) L.a[d] = take(nd);
@@ -220,6 +221,9 @@ gd_status gd_init(gd_ctx** out, const gd_params* p, int64_t n, const double* m, 
   if (!(p->eta > 0.0) || !std::isfinite(p->eta)) return bad(GD_EINVAL, "eta must be finite and > 0");
   if (!(p->eps == 0.0 || (p->eps >= 1e-30 && std::isfinite(p->eps))))
     return bad(GD_EINVAL, "eps must be 0 or in [1e-30, inf)");
+  if (p->bh_index < -1 || p->bh_index >= n) return bad(GD_EINVAL, "bh_index must be -1 or in [0, n)");
+  if (p->bh_index >= 0 && !(p->eps >= 1e-30 && p->eps_bh >= 1e-30 && std::isfinite(p->eps_bh)))
+    return bad(GD_EINVAL, "with a central particle, eps and eps_bh must be in [1e-30, inf)");
   if (!is_pow2(p->dt_max) || !is_pow2(p->dt_min) || p->dt_min > p->dt_max)
     return bad(GD_EINVAL, "dt_max and dt_min must be powers of two with dt_min <= dt_max");
   int kmax = (int)std::lround(std::log2(p->dt_max / p->dt_min));
@@ -239,12 +243,15 @@ gd_status gd_init(gd_ctx** out, const gd_params* p, int64_t n, const double* m, 
   c->c.dt_max = p->dt_max;
   c->c.eta = p->eta;
   c->c.eps2 = p->eps * p->eps;
+  c->c.bh = (int)p->bh_index;
+  c->c.eps2_bh = p->bh_index >= 0 ? p->eps_bh * p->eps_bh : c->c.eps2;
   launch_grids((int)n, &c->c.force_grid, &c->c.correct_grid);
   c->stream = (hipStream_t)hip_stream;
   char* w = (char*)workspace;
   Dev& d = c->d;
   d.sc = (Sched*)(w + L.sc);
   d.m = (double*)(w + L.m);
+  d.jm = (double*)(w + L.jm);
   double** xs[3] = {&d.x, &d.y, &d.z};
   double** vs[3] = {&d.vx, &d.vy, &d.vz};
   double** as[3] = {&d.ax, &d.ay, &d.az};

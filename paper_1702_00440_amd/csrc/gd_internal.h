@@ -117,6 +117,7 @@ __host__ __device__ inline EPlan make_eplan(int n) {
 struct Dev {
   Sched* sc;
   double* m;
+  double* jm;                              // j-stream masses (central particle's zeroed)
   double *x, *y, *z, *vx, *vy, *vz;        // corrected state at t_i
   double *ax, *ay, *az, *jx, *jy, *jz;     // acceleration, jerk at t_i
   double *px, *py, *pz, *pvx, *pvy, *pvz;  // predicted j stream
@@ -135,7 +136,8 @@ struct Consts {
   int kmax;          // log2(dt_max / dt_min)
   int force_grid;    // workgroups of a force launch
   int correct_grid;  // workgroups of a corrector launch
-  double dt_min, dt_max, eta, eps2;
+  int bh;            // index of the central particle, -1 if none
+  double dt_min, dt_max, eta, eps2, eps2_bh;
 };
 
 // Lanes the corrector gives one active particle: one per j slice of the

@@ -106,7 +106,7 @@ __device__ __forceinline__ double norm3(double a, double b, double c) {
 // The slices of a particle are summed afterwards by the kernel that consumes
 // the force (corrector, initial steps, or output), in an order that depends
 // only on (n_act, n).
-template <bool kMaskSelf>
+template <bool kMaskSelf, bool kCentral>
 __global__ __launch_bounds__(kBlock) void k_force(Dev d, Consts c) {
   const Sched* __restrict__ sc = d.sc;
   if (sc->done) return;
@@ -122,7 +122,9 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Consts c) {
   const double* __restrict__ pvx = d.pvx;
   const double* __restrict__ pvy = d.pvy;
   const double* __restrict__ pvz = d.pvz;
-  const double* __restrict__ pm = d.m;
+  // With a central particle its mass is zero in the j stream (jm); its pairs
+  // are added separately below with their own softening.
+  const double* __restrict__ pm = kCentral ? d.jm : d.m;
   double* __restrict__ part = d.part;
 
   __shared__ double sj[7][kTileJ];
@@ -140,7 +142,7 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Consts c) {
 
     int pos[kIPerLane], gi[kIPerLane];
     double xi[kIPerLane], yi[kIPerLane], zi[kIPerLane];
-    double vxi[kIPerLane], vyi[kIPerLane], vzi[kIPerLane];
+    double vxi[kIPerLane], vyi[kIPerLane], vzi[kIPerLane], e2i[kIPerLane];
     Acc6 A[kIPerLane];
 #pragma unroll
     for (int q = 0; q < kIPerLane; ++q) {
@@ -148,7 +150,10 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Consts c) {
       // The predicted state of the active list is stored by list position
       // (one load level instead of an index gather).
       const int k = min(pos[q], n_act - 1);
-      gi[q] = kMaskSelf ? d.active[k] : 0;
+      gi[q] = (kMaskSelf || kCentral) ? d.active[k] : 0;
+      // Softening enters only as the addend of r.r, so a per-i value costs
+      // nothing: the central particle takes eps_bh for all of its pairs.
+      e2i[q] = (kCentral && gi[q] == c.bh) ? c.eps2_bh : eps2;
       xi[q] = d.ix[k];
       yi[q] = d.iy[k];
       zi[q] = d.iz[k];
@@ -196,7 +201,7 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Consts c) {
           } else {
             // eps > 0: the j = i term is exactly zero (r = w = 0, finite q).
             pair_fp64(xi[q], yi[q], zi[q], vxi[q], vyi[q], vzi[q], xj, yj, zj, vxj, vyj, vzj, mj,
-                      eps2, A[q]);
+                      e2i[q], A[q]);
           }
         }
       }
@@ -213,6 +218,17 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Consts c) {
         A[q].jy += shfl_xor_d(A[q].jy, off);
         A[q].jz += shfl_xor_d(A[q].jz, off);
       }
+    }
+    if (kCentral && slice == 0 && jsub == 0) {
+      // The central particle as j, softened with eps_bh, once per i.
+      const int b = c.bh;
+      const double bx = px[b], by = py[b], bz = pz[b];
+      const double bvx = pvx[b], bvy = pvy[b], bvz = pvz[b], bm = d.m[b];
+#pragma unroll
+      for (int q = 0; q < kIPerLane; ++q)
+        if (gi[q] != b)
+          pair_fp64(xi[q], yi[q], zi[q], vxi[q], vyi[q], vzi[q], bx, by, bz, bvx, bvy, bvz, bm,
+                    c.eps2_bh, A[q]);
     }
     if (jsub == 0) {
 #pragma unroll
@@ -606,7 +622,8 @@ __global__ __launch_bounds__(kBlock) void k_predict(Sched* __restrict__ sc, int 
 // with the j = i term excluded, then the workgroup reduces -m_i phi_i / 2
 // (and the kinetic term, on slice 0) in a fixed tree. A second kernel sums
 // the item partials in a fixed order.
-__global__ __launch_bounds__(kBlock) void k_energy(int n, double eps2, int unsoft,
+__global__ __launch_bounds__(kBlock) void k_energy(int n, double eps2, double eps2_bh, int bh,
+                                                   int unsoft,
                                                    const double* __restrict__ x,
                                                    const double* __restrict__ y,
                                                    const double* __restrict__ z,
@@ -641,7 +658,8 @@ __global__ __launch_bounds__(kBlock) void k_energy(int n, double eps2, int unsof
         const bool self = (jt + k) == ii;
         const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
         const double mj = self ? 0.0 : sj[3][k];
-        phi = fma(mj, rsqrt_fp64(self ? 1.0 : r2 + eps2), phi);
+        const double e2 = (bh >= 0 && ((jt + k) == bh || ii == bh)) ? eps2_bh : eps2;
+        phi = fma(mj, rsqrt_fp64(self ? 1.0 : r2 + e2), phi);
         if (unsoft) phiu = fma(mj, rsqrt_fp64(self ? 1.0 : r2), phiu);
       }
     }
@@ -711,9 +729,10 @@ __device__ __forceinline__ bool fin3(double a, double b, double c) {
 }
 
 // Row-major (n, 3) inputs to SoA; masses copied; validation of the inputs.
-__global__ void k_load(Sched* __restrict__ sc, int n, const double* __restrict__ m_in,
+__global__ void k_load(Sched* __restrict__ sc, int n, int bh, const double* __restrict__ m_in,
                        const double* __restrict__ x_in, const double* __restrict__ v_in,
-                       double* __restrict__ m, double* __restrict__ x, double* __restrict__ y,
+                       double* __restrict__ m, double* __restrict__ jm, double* __restrict__ x,
+                       double* __restrict__ y,
                        double* __restrict__ z, double* __restrict__ vx, double* __restrict__ vy,
                        double* __restrict__ vz, double* __restrict__ ax, double* __restrict__ ay,
                        double* __restrict__ az, double* __restrict__ jx, double* __restrict__ jy,
@@ -726,6 +745,7 @@ __global__ void k_load(Sched* __restrict__ sc, int n, const double* __restrict__
   const double v0 = v_in[3 * i], v1 = v_in[3 * i + 1], v2 = v_in[3 * i + 2];
   if (!(isfinite(mi) && mi >= 0.0 && fin3(x0, x1, x2) && fin3(v0, v1, v2))) atomicOr(&sc->bad_input, 1);
   m[i] = mi;
+  jm[i] = i == bh ? 0.0 : mi;
   x[i] = x0; y[i] = x1; z[i] = x2;
   vx[i] = v0; vy[i] = v1; vz[i] = v2;
   ax[i] = 0; ay[i] = 0; az[i] = 0;
@@ -864,8 +884,8 @@ static inline int grid_for(int n) { return (n + kBlock - 1) / kBlock; }
 
 hipError_t launch_load(const Dev& d, const Consts& c, const double* m, const double* x,
                        const double* v, hipStream_t s) {
-  hipLaunchKernelGGL(k_load, dim3(grid_for(c.n)), dim3(kBlock), 0, s, d.sc, c.n, m, x, v, d.m,
-                     d.x, d.y, d.z, d.vx, d.vy, d.vz, d.ax, d.ay, d.az, d.jx, d.jy, d.jz, d.tick,
+  hipLaunchKernelGGL(k_load, dim3(grid_for(c.n)), dim3(kBlock), 0, s, d.sc, c.n, c.bh, m, x, v, d.m,
+                     d.jm, d.x, d.y, d.z, d.vx, d.vy, d.vz, d.ax, d.ay, d.az, d.jx, d.jy, d.jz, d.tick,
                      d.lev);
   return hipGetLastError();
 }
@@ -882,7 +902,7 @@ hipError_t launch_predict(const Dev& d, const Consts& c, int mode, double t_expl
 
 hipError_t launch_force(const Dev& d, const Consts& c, hipStream_t s, hipEvent_t ev_start,
                         hipEvent_t ev_stop) {
-  auto kern = c.eps2 > 0.0 ? k_force<false> : k_force<true>;
+  auto kern = c.bh >= 0 ? k_force<false, true> : (c.eps2 > 0.0 ? k_force<false, false> : k_force<true, false>);
   if (ev_start) {
     // The events take the dispatch's own start and end timestamps.
     hipExtLaunchKernelGGL(kern, dim3(c.force_grid), dim3(kBlock), 0, s, ev_start, ev_stop, 0, d, c);
@@ -909,8 +929,8 @@ hipError_t launch_reduce_out(const Dev& d, const Consts& c, double* acc, double*
 }
 
 hipError_t launch_energy(const Dev& d, const Consts& c, int unsoft, hipStream_t s) {
-  hipLaunchKernelGGL(k_energy, dim3(kEnergyGrid), dim3(kBlock), 0, s, c.n, c.eps2, unsoft, d.x,
-                     d.y, d.z, d.vx, d.vy, d.vz, d.m, d.ebuf);
+  hipLaunchKernelGGL(k_energy, dim3(kEnergyGrid), dim3(kBlock), 0, s, c.n, c.eps2, c.eps2_bh, c.bh,
+                     unsoft, d.x, d.y, d.z, d.vx, d.vy, d.vz, d.m, d.ebuf);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const EPlan ep = make_eplan(c.n);

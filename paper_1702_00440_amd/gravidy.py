@@ -30,8 +30,8 @@ class GdError(RuntimeError):
 
 
 class gd_params(C.Structure):
-    _fields_ = [("eta", C.c_double), ("eps", C.c_double), ("dt_max", C.c_double),
-                ("dt_min", C.c_double), ("flags", C.c_int32)]
+    _fields_ = [("eta", C.c_double), ("eps", C.c_double), ("eps_bh", C.c_double), ("dt_max", C.c_double),
+                ("dt_min", C.c_double), ("bh_index", C.c_int64), ("flags", C.c_int32)]
 
 
 class gd_stats(C.Structure):
@@ -108,8 +108,10 @@ def _stream_handle(stream=None) -> int:
     return s.cuda_stream
 
 
-def make_params(eta=0.01, eps=1e-4, dt_max=0.125, dt_min=2.0 ** -22, flags=0) -> gd_params:
-    return gd_params(float(eta), float(eps), float(dt_max), float(dt_min), int(flags))
+def make_params(eta=0.01, eps=1e-4, dt_max=0.125, dt_min=2.0 ** -22, flags=0, eps_bh=None,
+                bh_index=-1) -> gd_params:
+    e_bh = float(eps if eps_bh is None else eps_bh)
+    return gd_params(float(eta), float(eps), e_bh, float(dt_max), float(dt_min), int(bh_index), int(flags))
 
 
 def gd_workspace_bytes(n: int, params: gd_params | None = None) -> int:
@@ -216,8 +218,8 @@ class Cluster:
     """One context plus the device workspace it owns (a torch uint8 tensor)."""
 
     def __init__(self, m, x, v, eta=0.01, eps=1e-4, dt_max=0.125, dt_min=2.0 ** -22,
-                 device="cuda", stream=None):
-        self.params = make_params(eta, eps, dt_max, dt_min)
+                 device="cuda", stream=None, eps_bh=None, bh_index=-1):
+        self.params = make_params(eta, eps, dt_max, dt_min, eps_bh=eps_bh, bh_index=bh_index)
         dev = torch.device(device)
         self.m = torch.as_tensor(m, dtype=torch.float64).to(dev).contiguous()
         self.n = self.m.shape[0]

@@ -1,0 +1,84 @@
+"""Central massive particle (the paper's planned extension, Sec. 6): pairs
+that involve it are softened with eps_bh, all others with eps. Parity of the
+HIP path with the oracle on a Plummer sphere of 2048 stars plus a particle of
+mass 0.01 at rest at the origin (eps 1e-4, eps_bh 1e-6, dt_min 2^-22)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1702_00440_amd import gravidy as g
+from synth_inputs import plummer_with_bh
+from tests.gpu_util import DEV, host, rel_err_rows
+
+pytestmark = pytest.mark.gpu
+
+EPS, EPS_BH, ETA, DTMAX, DTMIN = 1e-4, 1e-6, 0.01, 0.125, 2.0 ** -22
+NS = 2048
+
+
+@pytest.fixture(scope="module")
+def system():
+    return plummer_with_bh(NS, 5)
+
+
+def _cluster(m, x, v):
+    return g.Cluster(m, x, v, eta=ETA, eps=EPS, dt_max=DTMAX, dt_min=DTMIN, device=DEV, eps_bh=EPS_BH,
+                     bh_index=NS)
+
+
+def _oracle_state(cl, m):
+    xs, vs, a, j, t_i, dt_i, t_now = cl.state()
+    return oracle.State.from_arrays(m, host(xs), host(vs), host(a), host(j), host(t_i), host(dt_i), t_now,
+                                    EPS, ETA, DTMAX, DTMIN, threads=oracle.max_threads(), eps_bh=EPS_BH, bh=NS)
+
+
+def test_initial_force_and_energy(system):
+    m, x, v = system
+    cl = _cluster(m, x, v)
+    _, _, a, j, _, _, _ = cl.state()
+    ra, rj = oracle.force(m, x, v, EPS, compensated=True, threads=oracle.max_threads(), eps_bh=EPS_BH, bh=NS)
+    assert rel_err_rows(host(a), ra).max() <= 1e-12
+    assert rel_err_rows(host(j), rj).max() <= 1e-12
+    ek, ep = g.gd_energy(cl.ctx)
+    rk, rp = oracle.energy(m, x, v, EPS, eps_bh=EPS_BH, bh=NS)
+    assert ek == pytest.approx(rk, rel=1e-13) and ep == pytest.approx(rp, rel=1e-13)
+    cl.close()
+
+
+def test_block_steps_from_identical_state(system):
+    m, x, v = system
+    cl = _cluster(m, x, v)
+    saw_bh = False
+    for _ in range(60):
+        ref = _oracle_state(cl, m)
+        act = ref.block_step()
+        saw_bh |= NS in act
+        g.gd_predict(cl.ctx)
+        idx = torch.empty(len(m), dtype=torch.int32, device=DEV)
+        n_act = g.gd_active(cl.ctx, idx)
+        np.testing.assert_array_equal(np.sort(host(idx[:n_act])), act)
+        g.gd_force(cl.ctx)
+        g.gd_correct(cl.ctx)
+        xs, vs, a, j, t_i, dt_i, t_now = cl.state()
+        assert t_now == ref.t_now
+        np.testing.assert_array_equal(host(dt_i), ref.dt_i)
+        assert rel_err_rows(host(xs), ref.x).max() <= 1e-13
+        assert rel_err_rows(host(a)[act], ref.a[act]).max() <= 1e-12
+        assert rel_err_rows(host(j)[act], ref.jk[act]).max() <= 1e-12
+    assert saw_bh
+    cl.close()
+
+
+def test_run_against_oracle(system):
+    m, x, v = system
+    cl = _cluster(m, x, v)
+    st = g.gd_step_to(cl.ctx, 0.125)
+    ref = oracle.State(m, x, v, EPS, ETA, DTMAX, DTMIN, threads=oracle.max_threads(), eps_bh=EPS_BH, bh=NS)
+    rows = ref.run(0.125)
+    assert st["block_steps"] == ref.stats[0]
+    assert st["particle_steps"] == ref.stats[1]
+    assert st["dtmin_clamps"] == ref.stats[3]
+    assert st["e"] == pytest.approx(rows[-1, 3], rel=1e-10)
+    assert np.abs(host(cl.state()[0]) - ref.x).max() < 1e-9
+    cl.close()

@@ -106,3 +106,13 @@ def test_null_context_is_rejected():
 def test_binding_refuses_host_tensors():
     with pytest.raises(TypeError):
         g._ptr(torch.zeros(3, dtype=torch.float64), torch.float64)
+
+
+def test_init_rejects_bad_central_particle():
+    lib = g.library()
+    ctx = C.c_void_p()
+    dummy = C.c_void_p(256)
+    for kw in [dict(bh_index=16), dict(bh_index=-2), dict(bh_index=3, eps_bh=0.0), dict(bh_index=3, eps=0.0)]:
+        p = g.make_params(**kw)
+        rc = lib.gd_init(C.byref(ctx), C.byref(p), 16, dummy, dummy, dummy, dummy, 1 << 30, None)
+        assert rc == g.GD_EINVAL, kw

@@ -21,9 +21,13 @@ MUTATIONS = [
     ("jerk factor 3 dropped", "w[d] / s32 - 3.0 * rw * r[d] / s52", "w[d] / s32 - rw * r[d] / s52"),
     ("acceleration power 3/2 -> 1", "double ta = m[j] * r[d] / s32;", "double ta = m[j] * r[d] / s;"),
     ("softening enters as eps, not eps^2",
-     "double eps2 = eps * eps;\n  set_threads(nthreads);", "double eps2 = eps;\n  set_threads(nthreads);"),
+     "double eps2 = eps * eps;\n  double eps2_bh = eps_bh * eps_bh;\n  set_threads(nthreads);",
+     "double eps2 = eps;\n  double eps2_bh = eps_bh * eps_bh;\n  set_threads(nthreads);"),
     ("self term not skipped", "    if (j == i) continue;\n    double r[3], w[3];", "    double r[3], w[3];"),
-    ("potential sign", "neumaier_add(&sp, &cp, -mm / sqrt(r2 + eps2));", "neumaier_add(&sp, &cp, mm / sqrt(r2 + eps2));"),
+    ("potential sign", "neumaier_add(&sp, &cp, -mm / sqrt(r2 + pair_eps2(i, j, eps2, eps2_bh, bh)));",
+     "neumaier_add(&sp, &cp, mm / sqrt(r2 + pair_eps2(i, j, eps2, eps2_bh, bh)));"),
+    ("central-particle softening one-sided", "(bh >= 0 && (i == bh || j == bh))", "(bh >= 0 && i == bh)"),
+    ("central-particle softening ignored", "? eps2_bh : eps2;", "? eps2 : eps2;"),
     ("predictor jerk coefficient", "jk[q] * dt * dt * dt / 6.0", "jk[q] * dt * dt * dt / 2.0"),
     ("predictor velocity jerk term dropped", "vp[q] = v[q] + a[q] * dt + jk[q] * dt * dt / 2.0;",
      "vp[q] = v[q] + a[q] * dt;"),
@@ -60,6 +64,7 @@ PIN_CALLS = [
     lambda: pins.test_timestep_circular_orbit_closed_form(),
     lambda: pins.test_quantize_rules(),
     lambda: pins.test_block_scheduler_invariants(),
+    lambda: pins.test_central_particle_softening(),
 ]
 
 

@@ -192,6 +192,39 @@ def test_bruteforce_decimal(n, eps, seed):
     assert ep == pytest.approx(dp, rel=1e-14)
 
 
+def test_central_particle_softening():
+    """A central massive particle softened with its own eps_bh (pairs that
+    involve it use eps_bh, all others eps): m a = -grad U with the same rule;
+    Newton's third law holds; pairs without it are unchanged; eps_bh = eps
+    reproduces the plain sums; the particle's own acceleration follows the
+    softened two-body law of its nearest companion in a pair."""
+    m, x, v = _small_system(6, 21)
+    m[2] = 5.0
+    bh, eps, eps_bh = 2, 0.2, 0.05
+    acc, jrk = oracle.force(m, x, v, eps, eps_bh=eps_bh, bh=bh)
+    h = 1e-3
+    for i in range(len(m)):
+        for d in range(3):
+            def U(s):
+                xx = x.copy()
+                xx[i, d] += s
+                return oracle.energy(m, xx, v, eps, eps_bh=eps_bh, bh=bh)[1]
+            grad = (4 * (U(h) - U(-h)) / (2 * h) - (U(2 * h) - U(-2 * h)) / (4 * h)) / 3
+            assert -grad == pytest.approx(m[i] * acc[i, d], rel=1e-7, abs=1e-9)
+    np.testing.assert_allclose((m[:, None] * acc).sum(0), 0, atol=1e-13 * (m[:, None] * np.abs(acc)).sum())
+    np.testing.assert_allclose((m[:, None] * jrk).sum(0), 0, atol=1e-13 * (m[:, None] * np.abs(jrk)).sum())
+    same_a, same_j = oracle.force(m, x, v, eps, eps_bh=eps, bh=bh)
+    plain_a, plain_j = oracle.force(m, x, v, eps)
+    np.testing.assert_array_equal(same_a, plain_a)
+    np.testing.assert_array_equal(same_j, plain_j)
+    # two bodies: separation d, softened law a = M r / (d^2 + eps_bh^2)^(3/2) on each
+    m2 = np.array([0.5, 2.0])
+    x2 = np.array([[0.0, 0.0, 0.0], [0.3, 0.0, 0.0]])
+    a2, _ = oracle.force(m2, x2, np.zeros((2, 3)), eps, eps_bh=eps_bh, bh=1)
+    f = 0.3 / (0.09 + eps_bh ** 2) ** 1.5
+    np.testing.assert_allclose(a2[:, 0], [2.0 * f, -0.5 * f], rtol=1e-14)
+
+
 def test_plummer_mean_field():
     """A large Plummer sample: the mean radial acceleration in radial shells
     follows the model's -M r / (r^2 + b^2)^(3/2) with b = 3 pi / 16 (Henon
