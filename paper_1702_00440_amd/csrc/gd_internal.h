@@ -20,7 +20,11 @@ constexpr int kForceGrid = 1024;
 // Upper bound of the corrector grid.
 constexpr int kCorrectGrid = 2048;
 // A lane of the split-j layout keeps at least this many j per slice.
-constexpr int kMinJPerLane = 16;
+constexpr int kMinJPerLane = 4;
+// Shortest j slice (one LDS tile): it bounds the number of slice partials a
+// particle has (N / kMinSlice). Small blocks shorten each lane's serial
+// chain of pair evaluations with more lanes per i instead (LJ up to 64).
+constexpr int kMinSlice = kTileJ;
 // Smallest log2 of the lanes that share one i: i tiles hold at most
 // (kBlock >> kMinLj) * kIPerLane = 32 particles, which keeps the number of
 // j slices (and so the partial sums to reduce) small for large blocks.
@@ -32,6 +36,16 @@ constexpr int kMaxLevels = 41;
 
 // Predictor modes.
 enum : int { kPredAuto = 0, kPredAll = 1, kPredExplicit = 2 };
+
+// Decomposition of one force launch over (i tile, j slice) items.
+//   lj   : log2 of the lanes sharing one i (LJ = 1 << lj, 1..64, in one wave)
+//   it   : i particles per workgroup tile = (kBlock >> lj) * kIPerLane
+//   nit  : number of i tiles
+//   s    : number of j slices; item = itile * s + slice
+//   len  : j particles per slice
+struct Plan {
+  int lj, it, nit, s, len, items;
+};
 
 // Device-resident scheduling and bookkeeping record (lives in the workspace).
 struct Sched {
@@ -45,24 +59,16 @@ struct Sched {
   int nonfinite;     // set when a non-finite force or jerk is seen
   int bad_input;     // set by input / state validation
   long long block_steps, particle_steps, pairs, clamps;
+  Plan plan;                 // force decomposition of the step in flight
   int hist[kMaxLevels + 1];  // particles per level
 };
 
-// Decomposition of one force launch over (i tile, j slice) items.
-//   lj   : log2 of the lanes sharing one i (LJ = 1 << lj, 1..64, in one wave)
-//   it   : i particles per workgroup tile = (kBlock >> lj) * kIPerLane
-//   nit  : number of i tiles
-//   s    : number of j slices; item = itile * s + slice
-//   len  : j particles per slice
-struct Plan {
-  int lj, it, nit, s, len, items;
-};
-
-// The plan depends only on (n_act, n): every kernel that needs it recomputes
-// it, so the force kernel and the reduction inside the corrector agree.
+// The plan depends only on (n_act, n). The kernel that fixes n_act for a
+// step (predictor, or the explicit index list) stores it in the Sched record,
+// and the force kernel and every slice reduction read that one copy.
 __host__ __device__ inline Plan make_plan(int n_act, int n) {
   Plan p;
-  int max_s = (n + kTileJ - 1) / kTileJ;
+  int max_s = (n + kMinSlice - 1) / kMinSlice;
   if (max_s < 1) max_s = 1;
   int lj = kMinLj;
   for (;;) {

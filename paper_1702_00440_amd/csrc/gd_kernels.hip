@@ -113,7 +113,7 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Consts c) {
   const int n_act = sc->n_act;
   if (n_act <= 0) return;
   const int n = c.n;
-  const Plan p = make_plan(n_act, n);
+  const Plan p = sc->plan;
   if ((int)blockIdx.x >= p.items) return;
   const double eps2 = c.eps2;
   const double* __restrict__ px = d.px;
@@ -319,7 +319,7 @@ __global__ __launch_bounds__(kBlock) void k_correct(Dev d, Consts c) {
   if (sc->done) return;
   const int n_act = sc->n_act;
   const long long t_next = sc->t_next;
-  const Plan p = make_plan(n_act, c.n);
+  const Plan p = sc->plan;
   const int L = correct_lanes(p.s);
   const int per_wg = kBlock / L;
   const int tid = threadIdx.x;
@@ -404,7 +404,7 @@ __global__ __launch_bounds__(kBlock) void k_init_dt(Dev d, Consts c) {
   Sched* __restrict__ sc = d.sc;
   const int n_act = sc->n_act;
   const long long t_now = sc->t_now;
-  const Plan p = make_plan(n_act, c.n);
+  const Plan p = sc->plan;
   const int L = correct_lanes(p.s);
   const int per_wg = kBlock / L;
   const int tid = threadIdx.x;
@@ -442,7 +442,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_out(Dev d, Consts c, double* 
                                                        double* __restrict__ jerk) {
   Sched* __restrict__ sc = d.sc;
   const int n_act = sc->n_act;
-  const Plan p = make_plan(n_act, c.n);
+  const Plan p = sc->plan;
   const int L = correct_lanes(p.s);
   const int per_wg = kBlock / L;
   const int tid = threadIdx.x;
@@ -565,6 +565,7 @@ __global__ __launch_bounds__(kBlock) void k_predict(Sched* __restrict__ sc, int 
       sc->kthr = kthr;
       sc->n_act = nact;
       sc->done = done;
+      if (nact > 0) sc->plan = make_plan(nact, n);
     }
   }
   __syncthreads();
@@ -796,6 +797,7 @@ __global__ void k_set_active(Sched* __restrict__ sc, int n, const int32_t* __res
   if (k == 0) {
     sc->n_act = n_act;
     sc->done = 0;
+    sc->plan = make_plan(n_act, n);
   }
   if (k >= n_act) return;
   int i = idx[k];
