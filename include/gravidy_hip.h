@@ -203,6 +203,70 @@ gd_status gd_get_state(gd_ctx* c, double* x, double* v, double* a, double* jerk,
 gd_status gd_set_state(gd_ctx* c, const double* x, const double* v, const double* a,
                        const double* jerk, const double* t_i, const double* dt_i, double t_now);
 
+/*
+ * Pools: continuous batching of independent clusters.
+ *
+ * A pool integrates many independent clusters (each its own N, initial
+ * conditions and end time) that arrive over time. Each cluster follows the
+ * same method as a context (Sec. 2.4 steps 2-7). One pool step advances every
+ * resident cluster by one of its own block steps, with one launch per phase
+ * (predict, force, correct) for all of them together, so small clusters
+ * share the GPU instead of queueing for it. A cluster's decomposition depends
+ * only on its own (N_act, N): its results are bitwise the same whether it
+ * runs alone (in a pool or a context) or packed with others. Pools take
+ * softened clusters (eps > 0) without a central particle.
+ *
+ * Memory: the caller provides one device arena (256-byte aligned). It holds
+ * the pool tables and, first-fit, the workspace of every admitted cluster
+ * (gd_workspace_bytes(n) each) until it is released: admission is by device
+ * footprint.
+ */
+typedef struct gd_pool gd_pool;
+
+/* Arena bytes for max_clusters slots plus the workspaces of `count` clusters
+ * of sizes n[0..count) resident at once (host-only). max_clusters <= 64. */
+gd_status gd_pool_arena_bytes(int32_t max_clusters, const int64_t* n, int32_t count, size_t* bytes);
+
+/* Create an empty pool. p: parameters shared by every cluster (bh_index -1,
+ * eps > 0). Errors: GD_EINVAL, GD_ENOMEM (arena too small for the tables),
+ * GD_EHIP. Synchronises. */
+gd_status gd_pool_create(gd_pool** pool, const gd_params* p, int32_t max_clusters, void* arena,
+                         size_t arena_bytes, void* hip_stream);
+
+/* Admit one cluster: masses m[n], positions x[n][3], velocities v[n][3]
+ * (device arrays, copied in) at t = 0, to be integrated to t_end (host
+ * value, a positive multiple of dt_max). Runs the cluster's initialisation
+ * (initial force, steps, energy) and makes it resident; *slot receives its
+ * slot. Returns GD_ENOMEM, with nothing changed, when no slot or no arena gap
+ * of gd_workspace_bytes(n) is free (retry after a release). Synchronises. */
+gd_status gd_pool_admit(gd_pool* pool, int64_t n, const double* m, const double* x, const double* v,
+                        double t_end, int32_t* slot);
+
+/* Advance every resident cluster by up to 32 of its own block steps (one
+ * graph replay). Clusters that reached their end time (or produced a
+ * non-finite force) stop being resident; their slots are written to
+ * finished (host, capacity 64, may be NULL) and counted in *n_finished.
+ * Synchronises. */
+gd_status gd_pool_run(gd_pool* pool, int32_t* finished, int32_t* n_finished);
+
+/* Final state of a finished cluster: x, v device (n, 3) outputs (either may
+ * be NULL); st (host, may be NULL) its statistics, with e0 and e the energy
+ * at t = 0 and t_end. Errors: GD_ESTATE while it runs, GD_ENONFINITE if it
+ * failed. Synchronises. */
+gd_status gd_pool_result(gd_pool* pool, int32_t slot, double* x, double* v, gd_stats* st);
+
+/* Free a slot and its arena block (a running cluster is dropped). */
+gd_status gd_pool_release(gd_pool* pool, int32_t slot);
+
+/* Number of resident (running) clusters (host output). */
+gd_status gd_pool_resident(gd_pool* pool, int32_t* count);
+
+/* Free the host side of the pool (not the arena). NULL is a no-op. */
+void gd_pool_destroy(gd_pool* pool);
+
+/* Message of the last failing call on pool (NULL: last gd_pool_create failure). */
+const char* gd_pool_last_error(const gd_pool* pool);
+
 /* Statistics (host output). Synchronises. */
 gd_status gd_stats_get(gd_ctx* c, gd_stats* st);
 

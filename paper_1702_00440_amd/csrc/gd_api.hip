@@ -14,7 +14,9 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <algorithm>
 #include <string>
+#include <vector>
 
 #include "gd_internal.h"
 #include "../../include/gravidy_hip.h"
@@ -70,10 +72,83 @@ Layout make_layout(long long n) {
   return L;
 }
 
+// Device pointers of a workspace laid out by make_layout.
+Dev carve(void* workspace, const Layout& L) {
+  char* w = (char*)workspace;
+  Dev d{};
+  d.sc = (Sched*)(w + L.sc);
+  d.m = (double*)(w + L.m);
+  d.jm = (double*)(w + L.jm);
+  double** xs[3] = {&d.x, &d.y, &d.z};
+  double** vs[3] = {&d.vx, &d.vy, &d.vz};
+  double** as[3] = {&d.ax, &d.ay, &d.az};
+  double** js[3] = {&d.jx, &d.jy, &d.jz};
+  double** ps[3] = {&d.px, &d.py, &d.pz};
+  double** pvs[3] = {&d.pvx, &d.pvy, &d.pvz};
+  for (int k = 0; k < 3; ++k) {
+    *xs[k] = (double*)(w + L.x[k]);
+    *vs[k] = (double*)(w + L.v[k]);
+    *as[k] = (double*)(w + L.a[k]);
+    *js[k] = (double*)(w + L.j[k]);
+    *ps[k] = (double*)(w + L.p[k]);
+    *pvs[k] = (double*)(w + L.pv[k]);
+  }
+  d.tick = (long long*)(w + L.tick);
+  d.lev = (int*)(w + L.lev);
+  d.active = (int*)(w + L.active);
+  double** is[3] = {&d.ix, &d.iy, &d.iz};
+  double** ivs[3] = {&d.ivx, &d.ivy, &d.ivz};
+  double** ias[3] = {&d.iax, &d.iay, &d.iaz};
+  double** ijs[3] = {&d.ijx, &d.ijy, &d.ijz};
+  for (int k = 0; k < 3; ++k) {
+    *is[k] = (double*)(w + L.ip[k]);
+    *ivs[k] = (double*)(w + L.ipv[k]);
+    *ias[k] = (double*)(w + L.ia[k]);
+    *ijs[k] = (double*)(w + L.ij[k]);
+  }
+  d.ilev = (int*)(w + L.ilev);
+  d.part = (double*)(w + L.part);
+  d.ebuf = (double*)(w + L.ebuf);
+  return d;
+}
+
 bool is_pow2(double v) {
   if (!(v > 0.0) || !std::isfinite(v)) return false;
   int e;
   return std::frexp(v, &e) == 0.5;
+}
+
+// Host-side validation shared by gd_init and gd_pool_admit; returns the
+// reason of the first failed check, or null.
+const char* check_params(const gd_params* p, int64_t n, int* kmax_out) {
+  if (n < 2 || n > (int64_t)std::numeric_limits<int>::max() / 2) return "n out of range";
+  if (!(p->eta > 0.0) || !std::isfinite(p->eta)) return "eta must be finite and > 0";
+  if (!(p->eps == 0.0 || (p->eps >= 1e-30 && std::isfinite(p->eps))))
+    return "eps must be 0 or in [1e-30, inf)";
+  if (p->bh_index < -1 || p->bh_index >= n) return "bh_index must be -1 or in [0, n)";
+  if (p->bh_index >= 0 && !(p->eps >= 1e-30 && p->eps_bh >= 1e-30 && std::isfinite(p->eps_bh)))
+    return "with a central particle, eps and eps_bh must be in [1e-30, inf)";
+  if (!is_pow2(p->dt_max) || !is_pow2(p->dt_min) || p->dt_min > p->dt_max)
+    return "dt_max and dt_min must be powers of two with dt_min <= dt_max";
+  const int kmax = (int)std::lround(std::log2(p->dt_max / p->dt_min));
+  if (kmax > 40) return "log2(dt_max / dt_min) must be <= 40";
+  if (p->flags != 0) return "flags must be 0";
+  *kmax_out = kmax;
+  return nullptr;
+}
+
+Consts make_consts(const gd_params* p, int64_t n, int kmax) {
+  Consts c{};
+  c.n = (int)n;
+  c.kmax = kmax;
+  c.dt_min = p->dt_min;
+  c.dt_max = p->dt_max;
+  c.eta = p->eta;
+  c.eps2 = p->eps * p->eps;
+  c.bh = (int)p->bh_index;
+  c.eps2_bh = p->bh_index >= 0 ? p->eps_bh * p->eps_bh : c.eps2;
+  launch_grids((int)n, &c.force_grid, &c.correct_grid);
+  return c;
 }
 
 }  // namespace
@@ -217,18 +292,8 @@ gd_status gd_init(gd_ctx** out, const gd_params* p, int64_t n, const double* m, 
     return st;
   };
   if (!p || !m || !x || !v || !workspace) return bad(GD_EINVAL, "NULL argument");
-  if (n < 2 || n > (int64_t)std::numeric_limits<int>::max() / 2) return bad(GD_EINVAL, "n out of range");
-  if (!(p->eta > 0.0) || !std::isfinite(p->eta)) return bad(GD_EINVAL, "eta must be finite and > 0");
-  if (!(p->eps == 0.0 || (p->eps >= 1e-30 && std::isfinite(p->eps))))
-    return bad(GD_EINVAL, "eps must be 0 or in [1e-30, inf)");
-  if (p->bh_index < -1 || p->bh_index >= n) return bad(GD_EINVAL, "bh_index must be -1 or in [0, n)");
-  if (p->bh_index >= 0 && !(p->eps >= 1e-30 && p->eps_bh >= 1e-30 && std::isfinite(p->eps_bh)))
-    return bad(GD_EINVAL, "with a central particle, eps and eps_bh must be in [1e-30, inf)");
-  if (!is_pow2(p->dt_max) || !is_pow2(p->dt_min) || p->dt_min > p->dt_max)
-    return bad(GD_EINVAL, "dt_max and dt_min must be powers of two with dt_min <= dt_max");
-  int kmax = (int)std::lround(std::log2(p->dt_max / p->dt_min));
-  if (kmax > 40) return bad(GD_EINVAL, "log2(dt_max / dt_min) must be <= 40");
-  if (p->flags != 0) return bad(GD_EINVAL, "flags must be 0");
+  int kmax = 0;
+  if (const char* why = check_params(p, n, &kmax)) return bad(GD_EINVAL, why);
   if (((uintptr_t)workspace & 255) != 0) return bad(GD_EINVAL, "workspace must be 256-byte aligned");
   const Layout L = make_layout(n);
   if (ws_bytes < L.total) return bad(GD_ENOMEM, "workspace smaller than gd_workspace_bytes()");
@@ -237,51 +302,10 @@ gd_status gd_init(gd_ctx** out, const gd_params* p, int64_t n, const double* m, 
   if (!c) return bad(GD_EINVAL, "out of host memory");
   c->p = *p;
   c->n = n;
-  c->c.n = (int)n;
-  c->c.kmax = kmax;
-  c->c.dt_min = p->dt_min;
-  c->c.dt_max = p->dt_max;
-  c->c.eta = p->eta;
-  c->c.eps2 = p->eps * p->eps;
-  c->c.bh = (int)p->bh_index;
-  c->c.eps2_bh = p->bh_index >= 0 ? p->eps_bh * p->eps_bh : c->c.eps2;
-  launch_grids((int)n, &c->c.force_grid, &c->c.correct_grid);
+  c->c = make_consts(p, n, kmax);
   c->stream = (hipStream_t)hip_stream;
-  char* w = (char*)workspace;
+  c->d = carve(workspace, L);
   Dev& d = c->d;
-  d.sc = (Sched*)(w + L.sc);
-  d.m = (double*)(w + L.m);
-  d.jm = (double*)(w + L.jm);
-  double** xs[3] = {&d.x, &d.y, &d.z};
-  double** vs[3] = {&d.vx, &d.vy, &d.vz};
-  double** as[3] = {&d.ax, &d.ay, &d.az};
-  double** js[3] = {&d.jx, &d.jy, &d.jz};
-  double** ps[3] = {&d.px, &d.py, &d.pz};
-  double** pvs[3] = {&d.pvx, &d.pvy, &d.pvz};
-  for (int k = 0; k < 3; ++k) {
-    *xs[k] = (double*)(w + L.x[k]);
-    *vs[k] = (double*)(w + L.v[k]);
-    *as[k] = (double*)(w + L.a[k]);
-    *js[k] = (double*)(w + L.j[k]);
-    *ps[k] = (double*)(w + L.p[k]);
-    *pvs[k] = (double*)(w + L.pv[k]);
-  }
-  d.tick = (long long*)(w + L.tick);
-  d.lev = (int*)(w + L.lev);
-  d.active = (int*)(w + L.active);
-  double** is[3] = {&d.ix, &d.iy, &d.iz};
-  double** ivs[3] = {&d.ivx, &d.ivy, &d.ivz};
-  double** ias[3] = {&d.iax, &d.iay, &d.iaz};
-  double** ijs[3] = {&d.ijx, &d.ijy, &d.ijz};
-  for (int k = 0; k < 3; ++k) {
-    *is[k] = (double*)(w + L.ip[k]);
-    *ivs[k] = (double*)(w + L.ipv[k]);
-    *ias[k] = (double*)(w + L.ia[k]);
-    *ijs[k] = (double*)(w + L.ij[k]);
-  }
-  d.ilev = (int*)(w + L.ilev);
-  d.part = (double*)(w + L.part);
-  d.ebuf = (double*)(w + L.ebuf);
 
   auto cleanup_fail = [&](gd_status st) {
     g_init_error = c->err;
@@ -528,6 +552,361 @@ void gd_destroy(gd_ctx* c) {
 const char* gd_last_error(const gd_ctx* c) {
   if (!c) return g_init_error.c_str();
   return c->err.c_str();
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Pools of independent clusters (continuous batching)
+// ===========================================================================
+//
+// A pool owns one caller-provided arena: the device tables (slot descriptors,
+// the table of resident clusters, the status array), then the clusters'
+// workspaces, placed first-fit as clusters are admitted and freed as they
+// are released. Admission is by footprint: a cluster is admitted when a slot
+// and a gap of gd_workspace_bytes(n) bytes are free. One call of
+// gd_pool_run replays a captured graph of kPoolSteps pool steps; each pool
+// step advances every resident cluster by one of its own block steps, with
+// one launch per phase for all of them. Clusters that reach their end time
+// stop (their steps become no-ops) and are reported.
+
+namespace {
+
+constexpr int kPoolSteps = 32;  // pool steps per captured graph
+
+struct PoolSlotHost {
+  bool used = false;      // slot holds a cluster (running or finished)
+  bool resident = false;  // in the device table (still stepping)
+  int64_t n = 0;
+  size_t off = 0, bytes = 0;  // workspace block in the arena
+  long long t_end = 0;
+  double e0 = 0.0;
+  gd_status status = GD_OK;
+  Dev d{};
+  Consts c{};
+};
+
+}  // namespace
+
+struct gd_pool {
+  gd_params p{};
+  int kmax = 0;
+  int max_clusters = 0;
+  hipStream_t stream = nullptr;
+  hipStream_t capture_stream = nullptr;
+  hipGraphExec_t graph = nullptr;
+  char* arena = nullptr;
+  size_t arena_bytes = 0, heap_off = 0;
+  PoolSlot* d_slots = nullptr;
+  PoolTable* d_tab = nullptr;
+  PoolStatus* d_status = nullptr;
+  PoolStatus* h_status = nullptr;  // pinned
+  PoolTable* h_tab = nullptr;      // pinned staging
+  PoolSlot* h_slot = nullptr;      // pinned staging
+  double* h_e = nullptr;           // pinned energy result
+  std::vector<PoolSlotHost> slots;
+  std::string err;
+
+  gd_status fail(gd_status st, const char* msg) {
+    err = msg;
+    return st;
+  }
+  gd_status hip(hipError_t e, const char* what) {
+    if (e == hipSuccess) return GD_OK;
+    err = std::string(what) + ": " + hipGetErrorString(e);
+    return GD_EHIP;
+  }
+};
+
+namespace {
+
+size_t pool_table_bytes(int max_clusters) {
+  return align_up(sizeof(PoolSlot) * (size_t)max_clusters) + align_up(sizeof(PoolTable)) +
+         align_up(sizeof(PoolStatus) * (size_t)max_clusters);
+}
+
+// First-fit placement of `bytes` in the arena heap, between the blocks of the
+// clusters that hold slots.
+bool pool_place(gd_pool* P, size_t bytes, size_t* off) {
+  std::vector<std::pair<size_t, size_t>> blocks;
+  for (const auto& s : P->slots)
+    if (s.used) blocks.push_back({s.off, s.bytes});
+  std::sort(blocks.begin(), blocks.end());
+  size_t cur = P->heap_off;
+  for (const auto& b : blocks) {
+    if (b.first >= cur + bytes) break;
+    cur = std::max(cur, align_up(b.first + b.second));
+  }
+  if (cur + bytes > P->arena_bytes) return false;
+  *off = cur;
+  return true;
+}
+
+// Uploads the table of resident clusters (stream-ordered).
+gd_status pool_upload_table(gd_pool* P) {
+  PoolTable& t = *P->h_tab;
+  t.count = 0;
+  int acc = 0;
+  for (int sl = 0; sl < P->max_clusters; ++sl) {
+    const PoolSlotHost& s = P->slots[sl];
+    if (!s.resident) continue;
+    t.order[t.count] = sl;
+    t.pred_off[t.count] = acc;
+    acc += (int)((s.n + kBlock - 1) / kBlock);
+    ++t.count;
+  }
+  t.pred_off[t.count] = acc;
+  GD_TRY(P->hip(hipMemcpyAsync(P->d_tab, P->h_tab, sizeof(PoolTable), hipMemcpyHostToDevice, P->stream),
+                "upload pool table"));
+  // The staging buffer is reused by the next call: wait for the copy.
+  return P->hip(hipStreamSynchronize(P->stream), "synchronise");
+}
+
+gd_status pool_energy(gd_pool* P, PoolSlotHost& s, double* e) {
+  GD_TRY(P->hip(launch_energy(s.d, s.c, 0, P->stream), "energy kernel"));
+  const double* res = s.d.ebuf + 3 * (size_t)make_eplan(s.c.n).items;
+  GD_TRY(P->hip(hipMemcpyAsync(P->h_e, res, 3 * sizeof(double), hipMemcpyDeviceToHost, P->stream),
+                "read energy"));
+  GD_TRY(P->hip(hipStreamSynchronize(P->stream), "synchronise"));
+  *e = P->h_e[0] + P->h_e[1];
+  return GD_OK;
+}
+
+gd_status pool_build_graph(gd_pool* P) {
+  if (P->graph) return GD_OK;
+  hipGraph_t g = nullptr;
+  GD_TRY(P->hip(hipStreamBeginCapture(P->capture_stream, hipStreamCaptureModeThreadLocal),
+                "begin capture"));
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < kPoolSteps && e == hipSuccess; ++k)
+    e = launch_pool_step(P->d_slots, P->d_tab, P->capture_stream);
+  if (e == hipSuccess) e = launch_pool_status(P->d_slots, P->d_tab, P->d_status, P->capture_stream);
+  hipError_t e2 = hipStreamEndCapture(P->capture_stream, &g);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return P->hip(e != hipSuccess ? e : e2, "capture pool graph");
+  }
+  e = hipGraphInstantiate(&P->graph, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  return P->hip(e, "instantiate pool graph");
+}
+
+}  // namespace
+
+extern "C" {
+
+gd_status gd_pool_arena_bytes(int32_t max_clusters, const int64_t* n, int32_t count, size_t* bytes) {
+  if (!bytes || max_clusters < 1 || max_clusters > kMaxPool || count < 0 || (count > 0 && !n))
+    return GD_EINVAL;
+  size_t b = pool_table_bytes(max_clusters);
+  for (int k = 0; k < count; ++k) {
+    if (n[k] < 2 || n[k] > (int64_t)std::numeric_limits<int>::max() / 2) return GD_EINVAL;
+    b += make_layout(n[k]).total;
+  }
+  *bytes = b;
+  return GD_OK;
+}
+
+gd_status gd_pool_create(gd_pool** out, const gd_params* p, int32_t max_clusters, void* arena,
+                         size_t arena_bytes, void* hip_stream) {
+  if (!out) return GD_EINVAL;
+  *out = nullptr;
+  auto bad = [](gd_status st, const char* msg) {
+    g_init_error = msg;
+    return st;
+  };
+  if (!p || !arena) return bad(GD_EINVAL, "NULL argument");
+  if (max_clusters < 1 || max_clusters > kMaxPool) return bad(GD_EINVAL, "max_clusters must be in [1, 64]");
+  int kmax = 0;
+  if (const char* why = check_params(p, 2, &kmax)) return bad(GD_EINVAL, why);
+  if (p->bh_index != -1 || !(p->eps > 0.0))
+    return bad(GD_EINVAL, "pools take softened clusters without a central particle (eps > 0, bh_index = -1)");
+  if (((uintptr_t)arena & 255) != 0) return bad(GD_EINVAL, "arena must be 256-byte aligned");
+  if (arena_bytes < pool_table_bytes(max_clusters)) return bad(GD_ENOMEM, "arena smaller than the pool tables");
+  gd_pool* P = new (std::nothrow) gd_pool();
+  if (!P) return bad(GD_EINVAL, "out of host memory");
+  P->p = *p;
+  P->kmax = kmax;
+  P->max_clusters = max_clusters;
+  P->stream = (hipStream_t)hip_stream;
+  P->arena = (char*)arena;
+  P->arena_bytes = arena_bytes;
+  P->slots.resize(max_clusters);
+  size_t off = 0;
+  P->d_slots = (PoolSlot*)(P->arena + off);
+  off += align_up(sizeof(PoolSlot) * (size_t)max_clusters);
+  P->d_tab = (PoolTable*)(P->arena + off);
+  off += align_up(sizeof(PoolTable));
+  P->d_status = (PoolStatus*)(P->arena + off);
+  off += align_up(sizeof(PoolStatus) * (size_t)max_clusters);
+  P->heap_off = off;
+  gd_status st = GD_OK;
+  if (st == GD_OK) st = P->hip(hipHostMalloc((void**)&P->h_status, sizeof(PoolStatus) * max_clusters, 0), "pinned status");
+  if (st == GD_OK) st = P->hip(hipHostMalloc((void**)&P->h_tab, sizeof(PoolTable), 0), "pinned table");
+  if (st == GD_OK) st = P->hip(hipHostMalloc((void**)&P->h_slot, sizeof(PoolSlot), 0), "pinned slot");
+  if (st == GD_OK) st = P->hip(hipHostMalloc((void**)&P->h_e, 4 * sizeof(double), 0), "pinned energy");
+  if (st == GD_OK)
+    st = P->hip(hipStreamCreateWithFlags(&P->capture_stream, hipStreamNonBlocking), "capture stream");
+  if (st == GD_OK) st = pool_upload_table(P);
+  if (st != GD_OK) {
+    g_init_error = P->err;
+    gd_pool_destroy(P);
+    return st;
+  }
+  *out = P;
+  return GD_OK;
+}
+
+gd_status gd_pool_admit(gd_pool* P, int64_t n, const double* m, const double* x, const double* v,
+                        double t_end, int32_t* slot_out) {
+  if (!P || !slot_out) return GD_EINVAL;
+  *slot_out = -1;
+  if (!m || !x || !v) return P->fail(GD_EINVAL, "NULL argument");
+  int kmax = 0;
+  if (const char* why = check_params(&P->p, n, &kmax)) return P->fail(GD_EINVAL, why);
+  const double q = t_end / P->p.dt_max;
+  if (!std::isfinite(t_end) || !(q > 0) || q != std::floor(q) || q > 9.0e15 / (1LL << kmax))
+    return P->fail(GD_EINVAL, "t_end must be a positive multiple of dt_max");
+  int sl = -1;
+  for (int k = 0; k < P->max_clusters; ++k)
+    if (!P->slots[k].used) {
+      sl = k;
+      break;
+    }
+  if (sl < 0) return P->fail(GD_ENOMEM, "no free slot");
+  const Layout L = make_layout(n);
+  size_t off = 0;
+  if (!pool_place(P, L.total, &off)) return P->fail(GD_ENOMEM, "no room in the arena");
+  PoolSlotHost& s = P->slots[sl];
+  s = PoolSlotHost();
+  s.used = true;
+  s.n = n;
+  s.off = off;
+  s.bytes = L.total;
+  s.t_end = (long long)q * (1LL << kmax);
+  s.d = carve(P->arena + off, L);
+  s.c = make_consts(&P->p, n, kmax);
+  // Initialisation of the cluster (Sec. 2.4 steps 2-3) on the pool stream.
+  auto undo = [&](gd_status st) {
+    s = PoolSlotHost();
+    return st;
+  };
+  gd_status st;
+  if ((st = P->hip(launch_reset_sched(s.d, 0, P->stream), "reset")) != GD_OK) return undo(st);
+  if ((st = P->hip(launch_load(s.d, s.c, m, x, v, P->stream), "load kernel")) != GD_OK) return undo(st);
+  if ((st = P->hip(launch_predict(s.d, s.c, kPredAll, 0.0, P->stream), "predict kernel")) != GD_OK)
+    return undo(st);
+  if ((st = P->hip(launch_force(s.d, s.c, P->stream), "force kernel")) != GD_OK) return undo(st);
+  if ((st = P->hip(launch_init_dt(s.d, s.c, P->stream), "init dt kernel")) != GD_OK) return undo(st);
+  if ((st = P->hip(launch_set_tend(s.d, s.t_end, P->stream), "prepare")) != GD_OK) return undo(st);
+  Sched chk;
+  if ((st = P->hip(hipMemcpyAsync(&chk, s.d.sc, sizeof(Sched), hipMemcpyDeviceToHost, P->stream),
+                   "read status")) != GD_OK)
+    return undo(st);
+  if ((st = P->hip(hipStreamSynchronize(P->stream), "synchronise")) != GD_OK) return undo(st);
+  if (chk.bad_input) return undo(P->fail(GD_EINVAL, "non-finite or negative input (m, x or v)"));
+  if (chk.nonfinite) return undo(P->fail(GD_ENONFINITE, "non-finite initial acceleration or jerk"));
+  if ((st = pool_energy(P, s, &s.e0)) != GD_OK) return undo(st);
+  // Descriptor, then the table that makes the cluster resident.
+  P->h_slot->d = s.d;
+  P->h_slot->c = s.c;
+  if ((st = P->hip(hipMemcpyAsync(&P->d_slots[sl], P->h_slot, sizeof(PoolSlot), hipMemcpyHostToDevice,
+                                  P->stream),
+                   "upload slot")) != GD_OK)
+    return undo(st);
+  s.resident = true;
+  if ((st = pool_upload_table(P)) != GD_OK) return undo(st);
+  *slot_out = sl;
+  return GD_OK;
+}
+
+gd_status gd_pool_run(gd_pool* P, int32_t* finished, int32_t* n_finished) {
+  if (!P || !n_finished) return GD_EINVAL;
+  *n_finished = 0;
+  int resident = 0;
+  for (const auto& s : P->slots) resident += s.resident;
+  if (resident == 0) return GD_OK;
+  GD_TRY(pool_build_graph(P));
+  GD_TRY(P->hip(hipGraphLaunch(P->graph, P->stream), "pool graph launch"));
+  GD_TRY(P->hip(hipMemcpyAsync(P->h_status, P->d_status, sizeof(PoolStatus) * P->max_clusters,
+                               hipMemcpyDeviceToHost, P->stream),
+                "read pool status"));
+  GD_TRY(P->hip(hipStreamSynchronize(P->stream), "synchronise"));
+  bool changed = false;
+  for (int sl = 0; sl < P->max_clusters; ++sl) {
+    PoolSlotHost& s = P->slots[sl];
+    if (!s.resident) continue;
+    const PoolStatus& st = P->h_status[sl];
+    const bool failed = st.nonfinite != 0;
+    if (st.t_now >= s.t_end || failed) {
+      s.resident = false;
+      s.status = failed ? GD_ENONFINITE : GD_OK;
+      changed = true;
+      if (finished) finished[*n_finished] = sl;
+      ++*n_finished;
+    }
+  }
+  if (changed) GD_TRY(pool_upload_table(P));
+  return GD_OK;
+}
+
+gd_status gd_pool_result(gd_pool* P, int32_t sl, double* x, double* v, gd_stats* st) {
+  if (!P || sl < 0 || sl >= P->max_clusters) return GD_EINVAL;
+  PoolSlotHost& s = P->slots[sl];
+  if (!s.used) return P->fail(GD_EINVAL, "slot holds no cluster");
+  if (s.resident) return P->fail(GD_ESTATE, "cluster still running");
+  if (s.status != GD_OK) return P->fail(s.status, "cluster produced a non-finite acceleration or jerk");
+  if (x || v) GD_TRY(P->hip(launch_get_state(s.d, s.c, x, v, nullptr, nullptr, nullptr, nullptr, P->stream),
+                            "get state"));
+  if (st) {
+    double e = 0.0;
+    GD_TRY(pool_energy(P, s, &e));
+    const PoolStatus& ps = P->h_status[sl];
+    st->t = (double)ps.t_now * s.c.dt_min;
+    st->block_steps = ps.block_steps;
+    st->particle_steps = ps.particle_steps;
+    st->pair_interactions = ps.pairs;
+    st->dtmin_clamps = ps.clamps;
+    st->e0 = s.e0;
+    st->e = e;
+  } else {
+    GD_TRY(P->hip(hipStreamSynchronize(P->stream), "synchronise"));
+  }
+  return GD_OK;
+}
+
+gd_status gd_pool_release(gd_pool* P, int32_t sl) {
+  if (!P || sl < 0 || sl >= P->max_clusters) return GD_EINVAL;
+  PoolSlotHost& s = P->slots[sl];
+  if (!s.used) return P->fail(GD_EINVAL, "slot holds no cluster");
+  const bool was_resident = s.resident;
+  s = PoolSlotHost();
+  if (was_resident) GD_TRY(pool_upload_table(P));
+  return GD_OK;
+}
+
+gd_status gd_pool_resident(gd_pool* P, int32_t* count) {
+  if (!P || !count) return GD_EINVAL;
+  int c = 0;
+  for (const auto& s : P->slots) c += s.resident;
+  *count = c;
+  return GD_OK;
+}
+
+void gd_pool_destroy(gd_pool* P) {
+  if (!P) return;
+  if (P->graph) (void)hipGraphExecDestroy(P->graph);
+  if (P->capture_stream) (void)hipStreamDestroy(P->capture_stream);
+  if (P->h_status) (void)hipHostFree(P->h_status);
+  if (P->h_tab) (void)hipHostFree(P->h_tab);
+  if (P->h_slot) (void)hipHostFree(P->h_slot);
+  if (P->h_e) (void)hipHostFree(P->h_e);
+  delete P;
+}
+
+const char* gd_pool_last_error(const gd_pool* P) {
+  if (!P) return g_init_error.c_str();
+  return P->err.c_str();
 }
 
 }  // extern "C"

@@ -96,10 +96,13 @@ __host__ __device__ inline Plan make_plan(int n_act, int n) {
 }
 
 // Rows of the partial-force buffer a context of n particles needs: for every
-// plan, s * n_act <= s * nit * it <= max(nit, kTargetItems) * it, it <= 32.
+// plan, s * n_act <= s * nit * it <= max(nit, kTargetItems) * it with
+// it <= 32, and s * n_act <= (n / kMinSlice rounded up) * n.
 inline long long partial_rows(long long n) {
   const long long it_max = (long long)(kBlock >> kMinLj) * kIPerLane;
-  return n + it_max + (long long)kTargetItems * it_max;
+  const long long by_items = n + it_max + (long long)kTargetItems * it_max;
+  const long long by_slices = ((n + kMinSlice - 1) / kMinSlice) * n;
+  return by_items < by_slices ? by_items : by_slices;
 }
 
 // Energy decomposition: items are (i tile of kBlock, j slice).
@@ -172,6 +175,36 @@ inline void launch_grids(int n, int* force_grid, int* correct_grid) {
   *force_grid = (int)(fmax < kForceGrid ? fmax : kForceGrid);
   *correct_grid = (int)(cmax < kCorrectGrid ? cmax : kCorrectGrid);
 }
+
+// ---------------------------------------------------------------------------
+// Pools of independent clusters (continuous batching)
+// ---------------------------------------------------------------------------
+// A pool keeps up to kMaxPool clusters resident; one pool step advances every
+// resident cluster by one of its own block steps, with one launch per phase
+// (predict, force, correct) for all of them. The tables live in device memory
+// at the head of the pool's arena.
+constexpr int kMaxPool = 64;
+
+struct PoolSlot {
+  Dev d;
+  Consts c;
+};
+
+struct PoolTable {
+  int count;                   // resident clusters
+  int order[kMaxPool];         // slot index of each resident cluster
+  int pred_off[kMaxPool + 1];  // prefix sum of the clusters' predictor blocks
+};
+
+// Per-slot status gathered after each batch of pool steps.
+struct PoolStatus {
+  long long t_now, block_steps, particle_steps, pairs, clamps;
+  int done, nonfinite;
+};
+
+hipError_t launch_pool_step(const PoolSlot* slots, const PoolTable* tab, hipStream_t s);
+hipError_t launch_pool_status(const PoolSlot* slots, const PoolTable* tab, PoolStatus* out,
+                              hipStream_t s);
 
 // Launchers (gd_kernels.hip). Each returns the hipGetLastError() of its launch.
 hipError_t launch_load(const Dev& d, const Consts& c, const double* m, const double* x,

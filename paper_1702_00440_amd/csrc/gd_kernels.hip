@@ -107,14 +107,14 @@ __device__ __forceinline__ double norm3(double a, double b, double c) {
 // the force (corrector, initial steps, or output), in an order that depends
 // only on (n_act, n).
 template <bool kMaskSelf, bool kCentral>
-__global__ __launch_bounds__(kBlock) void k_force(Dev d, Consts c) {
+__device__ __forceinline__ void force_body(const Dev& d, const Consts& c, int blk, int nblk) {
   const Sched* __restrict__ sc = d.sc;
   if (sc->done) return;
   const int n_act = sc->n_act;
   if (n_act <= 0) return;
   const int n = c.n;
   const Plan p = sc->plan;
-  if ((int)blockIdx.x >= p.items) return;
+  if (blk >= p.items) return;
   const double eps2 = c.eps2;
   const double* __restrict__ px = d.px;
   const double* __restrict__ py = d.py;
@@ -134,7 +134,7 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Consts c) {
   const int ilane = tid >> p.lj;
   const int ilanes = kBlock >> p.lj;
 
-  for (int item = blockIdx.x; item < p.items; item += gridDim.x) {
+  for (int item = blk; item < p.items; item += nblk) {
     const int itile = item / p.s;
     const int slice = item - itile * p.s;
     const int j0 = slice * p.len;
@@ -247,6 +247,11 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Consts c) {
   }
 }
 
+template <bool kMaskSelf, bool kCentral>
+__global__ __launch_bounds__(kBlock) void k_force(Dev d, Consts c) {
+  force_body<kMaskSelf, kCentral>(d, c, blockIdx.x, gridDim.x);
+}
+
 // ---------------------------------------------------------------------------
 // Slice reduction and per-particle finishing
 // ---------------------------------------------------------------------------
@@ -314,7 +319,7 @@ __device__ __forceinline__ bool finite6(const double f[6]) {
 // Everything the particle needs (slice partials, predicted state, a0, j0,
 // level) is read by list position in one memory round trip; L lanes per
 // particle share the slice reduction and the first lane corrects.
-__global__ __launch_bounds__(kBlock) void k_correct(Dev d, Consts c) {
+__device__ __forceinline__ void correct_body(const Dev& d, const Consts& c, int blk, int nblk) {
   Sched* __restrict__ sc = d.sc;
   if (sc->done) return;
   const int n_act = sc->n_act;
@@ -323,11 +328,11 @@ __global__ __launch_bounds__(kBlock) void k_correct(Dev d, Consts c) {
   const int L = correct_lanes(p.s);
   const int per_wg = kBlock / L;
   const int tid = threadIdx.x;
-  if ((int)blockIdx.x * per_wg >= n_act && blockIdx.x != 0) return;
+  if (blk * per_wg >= n_act && blk != 0) return;
   __shared__ LocalBook bk;
   book_init(bk, tid);
   __syncthreads();
-  if (blockIdx.x == 0 && tid == 0) {
+  if (blk == 0 && tid == 0) {
     sc->block_steps += 1;
     sc->particle_steps += n_act;
     sc->pairs += (long long)n_act * c.n;
@@ -335,7 +340,7 @@ __global__ __launch_bounds__(kBlock) void k_correct(Dev d, Consts c) {
     sc->cnt = 0;
   }
   const int r = tid & (L - 1);
-  for (int base = blockIdx.x * per_wg; base < n_act; base += gridDim.x * per_wg) {
+  for (int base = blk * per_wg; base < n_act; base += nblk * per_wg) {
     const int k = base + tid / L;
     const bool valid = k < n_act;
     const int kk = valid ? k : 0;
@@ -394,6 +399,10 @@ __global__ __launch_bounds__(kBlock) void k_correct(Dev d, Consts c) {
   }
   __syncthreads();
   book_flush(bk, sc, c.kmax, tid);
+}
+
+__global__ __launch_bounds__(kBlock) void k_correct(Dev d, Consts c) {
+  correct_body(d, c, blockIdx.x, gridDim.x);
 }
 
 // Initial block steps (Sec. 2.4 step 3; Sec. 3.2: the same eta from the
@@ -483,46 +492,51 @@ __global__ __launch_bounds__(kBlock) void k_reduce_out(Dev d, Consts c, double* 
 // list order is not deterministic, but no result depends on it), together
 // with their predicted state (for the force kernel) and their a, jerk and
 // level (for the corrector), stored by list position.
-__global__ __launch_bounds__(kBlock) void k_predict(Sched* __restrict__ sc, int n, int kmax,
-                                                    double dt_min, int mode, double t_explicit,
-                                                    const double* __restrict__ x,
-                                                    const double* __restrict__ y,
-                                                    const double* __restrict__ z,
-                                                    const double* __restrict__ vx,
-                                                    const double* __restrict__ vy,
-                                                    const double* __restrict__ vz,
-                                                    const double* __restrict__ ax,
-                                                    const double* __restrict__ ay,
-                                                    const double* __restrict__ az,
-                                                    const double* __restrict__ jx,
-                                                    const double* __restrict__ jy,
-                                                    const double* __restrict__ jz,
-                                                    const long long* __restrict__ tick,
-                                                    const int* __restrict__ lev,
-                                                    double* __restrict__ px, double* __restrict__ py,
-                                                    double* __restrict__ pz,
-                                                    double* __restrict__ pvx,
-                                                    double* __restrict__ pvy,
-                                                    double* __restrict__ pvz,
-                                                    int* __restrict__ active,
-                                                    double* __restrict__ ix, double* __restrict__ iy,
-                                                    double* __restrict__ iz,
-                                                    double* __restrict__ ivx,
-                                                    double* __restrict__ ivy,
-                                                    double* __restrict__ ivz,
-                                                    double* __restrict__ iax,
-                                                    double* __restrict__ iay,
-                                                    double* __restrict__ iaz,
-                                                    double* __restrict__ ijx,
-                                                    double* __restrict__ ijy,
-                                                    double* __restrict__ ijz,
-                                                    int* __restrict__ ilev) {
+__device__ __forceinline__ void predict_body(const Dev& d, const Consts& c, int mode,
+                                             double t_explicit, int blk) {
+  Sched* __restrict__ sc = d.sc;
+  const int n = c.n, kmax = c.kmax;
+  const double dt_min = c.dt_min;
+  const double* __restrict__ x = d.x;
+  const double* __restrict__ y = d.y;
+  const double* __restrict__ z = d.z;
+  const double* __restrict__ vx = d.vx;
+  const double* __restrict__ vy = d.vy;
+  const double* __restrict__ vz = d.vz;
+  const double* __restrict__ ax = d.ax;
+  const double* __restrict__ ay = d.ay;
+  const double* __restrict__ az = d.az;
+  const double* __restrict__ jx = d.jx;
+  const double* __restrict__ jy = d.jy;
+  const double* __restrict__ jz = d.jz;
+  const long long* __restrict__ tick = d.tick;
+  const int* __restrict__ lev = d.lev;
+  double* __restrict__ px = d.px;
+  double* __restrict__ py = d.py;
+  double* __restrict__ pz = d.pz;
+  double* __restrict__ pvx = d.pvx;
+  double* __restrict__ pvy = d.pvy;
+  double* __restrict__ pvz = d.pvz;
+  int* __restrict__ active = d.active;
+  double* __restrict__ ix = d.ix;
+  double* __restrict__ iy = d.iy;
+  double* __restrict__ iz = d.iz;
+  double* __restrict__ ivx = d.ivx;
+  double* __restrict__ ivy = d.ivy;
+  double* __restrict__ ivz = d.ivz;
+  double* __restrict__ iax = d.iax;
+  double* __restrict__ iay = d.iay;
+  double* __restrict__ iaz = d.iaz;
+  double* __restrict__ ijx = d.ijx;
+  double* __restrict__ ijy = d.ijy;
+  double* __restrict__ ijz = d.ijz;
+  int* __restrict__ ilev = d.ilev;
   __shared__ long long s_tnow, s_tend, s_tnext;
   __shared__ int s_hist[kMaxLevels + 1];
   __shared__ int s_kthr, s_done, s_base;
   __shared__ int s_wcount[kBlock / 64];
   const int tid = threadIdx.x;
-  const int j = blockIdx.x * kBlock + tid;
+  const int j = blk * kBlock + tid;
   // The particle's state does not depend on the schedule: its loads are
   // issued first and overlap the read of the histogram and the clock.
   const int jj = min(j, n - 1);
@@ -560,7 +574,7 @@ __global__ __launch_bounds__(kBlock) void k_predict(Sched* __restrict__ sc, int 
     s_tnext = t_next;
     s_kthr = kthr;
     s_done = done;
-    if (blockIdx.x == 0) {
+    if (blk == 0) {
       sc->t_next = t_next;
       sc->kthr = kthr;
       sc->n_act = nact;
@@ -613,6 +627,10 @@ __global__ __launch_bounds__(kBlock) void k_predict(Sched* __restrict__ sc, int 
     ijx[k] = j_x; ijy[k] = j_y; ijz[k] = j_z;
     ilev[k] = lj;
   }
+}
+
+__global__ __launch_bounds__(kBlock) void k_predict(Dev d, Consts c, int mode, double t_explicit) {
+  predict_body(d, c, mode, t_explicit, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -879,6 +897,121 @@ __global__ void k_set_state(Sched* __restrict__ sc, int n, int kmax, double dt_m
 }
 
 // ---------------------------------------------------------------------------
+// Pool kernels: one launch per phase for every resident cluster
+// ---------------------------------------------------------------------------
+//
+// Each cluster keeps its own decomposition, which depends only on its own
+// (n_act, n): a pool launch assigns every workgroup task (a predictor block,
+// a force item, or a corrector block of one cluster) to the same body the
+// single-cluster kernels run. So a cluster's results are bitwise the same
+// alone and packed with others.
+
+constexpr int kPoolGrid = 1024;
+
+// Finds the entry k with off[k] <= g < off[k + 1] (count entries, off in LDS).
+__device__ __forceinline__ int pool_find(const int* off, int count, int g) {
+  int k = 0;
+  while (k + 1 < count && off[k + 1] <= g) ++k;
+  return k;
+}
+
+__global__ __launch_bounds__(kBlock) void k_pool_predict(const PoolSlot* __restrict__ slots,
+                                                         const PoolTable* __restrict__ tab) {
+  __shared__ int s_off[kMaxPool + 1], s_order[kMaxPool];
+  const int tid = threadIdx.x;
+  const int count = tab->count;
+  if (tid <= count) s_off[tid] = tab->pred_off[tid];
+  if (tid < count) s_order[tid] = tab->order[tid];
+  __syncthreads();
+  const int total = s_off[count];
+  for (int g = blockIdx.x; g < total; g += gridDim.x) {
+    const int k = pool_find(s_off, count, g);
+    const PoolSlot& ps = slots[s_order[k]];
+    predict_body(ps.d, ps.c, kPredAuto, 0.0, g - s_off[k]);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_pool_force(const PoolSlot* __restrict__ slots,
+                                                       const PoolTable* __restrict__ tab) {
+  __shared__ int s_off[kMaxPool + 1], s_order[kMaxPool], s_n[kMaxPool];
+  const int tid = threadIdx.x;
+  const int count = tab->count;
+  if (tid < count) {
+    const int sl = tab->order[tid];
+    const Sched* sc = slots[sl].d.sc;
+    s_order[tid] = sl;
+    s_n[tid] = (sc->done || sc->n_act <= 0) ? 0 : sc->plan.items;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int acc = 0;
+    for (int k = 0; k < count; ++k) {
+      s_off[k] = acc;
+      acc += s_n[k];
+    }
+    s_off[count] = acc;
+  }
+  __syncthreads();
+  const int total = s_off[count];
+  for (int g = blockIdx.x; g < total; g += gridDim.x) {
+    const int k = pool_find(s_off, count, g);
+    const PoolSlot& ps = slots[s_order[k]];
+    force_body<false, false>(ps.d, ps.c, g - s_off[k], s_n[k]);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_pool_correct(const PoolSlot* __restrict__ slots,
+                                                         const PoolTable* __restrict__ tab) {
+  __shared__ int s_off[kMaxPool + 1], s_order[kMaxPool], s_n[kMaxPool];
+  const int tid = threadIdx.x;
+  const int count = tab->count;
+  if (tid < count) {
+    const int sl = tab->order[tid];
+    const Sched* sc = slots[sl].d.sc;
+    s_order[tid] = sl;
+    int blocks = 0;
+    if (!sc->done && sc->n_act > 0) {
+      const int per_wg = kBlock / correct_lanes(sc->plan.s);
+      blocks = (sc->n_act + per_wg - 1) / per_wg;
+    }
+    s_n[tid] = blocks;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int acc = 0;
+    for (int k = 0; k < count; ++k) {
+      s_off[k] = acc;
+      acc += s_n[k];
+    }
+    s_off[count] = acc;
+  }
+  __syncthreads();
+  const int total = s_off[count];
+  for (int g = blockIdx.x; g < total; g += gridDim.x) {
+    const int k = pool_find(s_off, count, g);
+    const PoolSlot& ps = slots[s_order[k]];
+    correct_body(ps.d, ps.c, g - s_off[k], s_n[k]);
+  }
+}
+
+__global__ void k_pool_status(const PoolSlot* __restrict__ slots, const PoolTable* __restrict__ tab,
+                              PoolStatus* __restrict__ out) {
+  const int t = threadIdx.x;
+  if (t >= tab->count) return;
+  const int sl = tab->order[t];
+  const Sched* sc = slots[sl].d.sc;
+  PoolStatus st;
+  st.t_now = sc->t_now;
+  st.block_steps = sc->block_steps;
+  st.particle_steps = sc->particle_steps;
+  st.pairs = sc->pairs;
+  st.clamps = sc->clamps;
+  st.done = sc->done;
+  st.nonfinite = sc->nonfinite;
+  out[sl] = st;
+}
+
+// ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
 
@@ -894,11 +1027,7 @@ hipError_t launch_load(const Dev& d, const Consts& c, const double* m, const dou
 
 hipError_t launch_predict(const Dev& d, const Consts& c, int mode, double t_explicit,
                           hipStream_t s) {
-  hipLaunchKernelGGL(k_predict, dim3(grid_for(c.n)), dim3(kBlock), 0, s, d.sc, c.n, c.kmax,
-                     c.dt_min, mode, t_explicit, d.x, d.y, d.z, d.vx, d.vy, d.vz, d.ax, d.ay,
-                     d.az, d.jx, d.jy, d.jz, d.tick, d.lev, d.px, d.py, d.pz, d.pvx, d.pvy,
-                     d.pvz, d.active, d.ix, d.iy, d.iz, d.ivx, d.ivy, d.ivz, d.iax, d.iay, d.iaz,
-                     d.ijx, d.ijy, d.ijz, d.ilev);
+  hipLaunchKernelGGL(k_predict, dim3(grid_for(c.n)), dim3(kBlock), 0, s, d, c, mode, t_explicit);
   return hipGetLastError();
 }
 
@@ -978,6 +1107,23 @@ hipError_t launch_set_state(const Dev& d, const Consts& c, const double* x, cons
   hipLaunchKernelGGL(k_set_state, dim3(grid_for(c.n)), dim3(kBlock), 0, s, d.sc, c.n, c.kmax,
                      c.dt_min, t_now, x, v, a, jerk, t_i, dt_i, d.x, d.y, d.z, d.vx, d.vy, d.vz,
                      d.ax, d.ay, d.az, d.jx, d.jy, d.jz, d.tick, d.lev);
+  return hipGetLastError();
+}
+
+hipError_t launch_pool_step(const PoolSlot* slots, const PoolTable* tab, hipStream_t s) {
+  hipLaunchKernelGGL(k_pool_predict, dim3(kPoolGrid), dim3(kBlock), 0, s, slots, tab);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_pool_force, dim3(kPoolGrid), dim3(kBlock), 0, s, slots, tab);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_pool_correct, dim3(kPoolGrid), dim3(kBlock), 0, s, slots, tab);
+  return hipGetLastError();
+}
+
+hipError_t launch_pool_status(const PoolSlot* slots, const PoolTable* tab, PoolStatus* out,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_pool_status, dim3(1), dim3(kMaxPool), 0, s, slots, tab, out);
   return hipGetLastError();
 }
 

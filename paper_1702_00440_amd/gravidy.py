@@ -74,6 +74,20 @@ def library():
     for name in ["gd_workspace_bytes", "gd_init", "gd_reinit", "gd_profile_force", "gd_profile_get", "gd_predict", "gd_force", "gd_active", "gd_correct",
                  "gd_step_to", "gd_energy", "gd_get_state", "gd_set_state", "gd_stats_get"]:
         getattr(lib, name).restype = st
+    lib.gd_pool_arena_bytes.argtypes = [C.c_int32, C.POINTER(i64), C.c_int32, C.POINTER(C.c_size_t)]
+    lib.gd_pool_create.argtypes = [C.POINTER(_VP), C.POINTER(gd_params), C.c_int32, _VP, C.c_size_t, _VP]
+    lib.gd_pool_admit.argtypes = [_VP, i64, _VP, _VP, _VP, C.c_double, C.POINTER(C.c_int32)]
+    lib.gd_pool_run.argtypes = [_VP, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    lib.gd_pool_result.argtypes = [_VP, C.c_int32, _VP, _VP, C.POINTER(gd_stats)]
+    lib.gd_pool_release.argtypes = [_VP, C.c_int32]
+    lib.gd_pool_resident.argtypes = [_VP, C.POINTER(C.c_int32)]
+    for name in ["gd_pool_arena_bytes", "gd_pool_create", "gd_pool_admit", "gd_pool_run", "gd_pool_result",
+                 "gd_pool_release", "gd_pool_resident"]:
+        getattr(lib, name).restype = st
+    lib.gd_pool_destroy.argtypes = [_VP]
+    lib.gd_pool_destroy.restype = None
+    lib.gd_pool_last_error.argtypes = [_VP]
+    lib.gd_pool_last_error.restype = C.c_char_p
     lib.gd_destroy.argtypes = [_VP]
     lib.gd_destroy.restype = None
     lib.gd_last_error.argtypes = [_VP]
@@ -85,6 +99,12 @@ def library():
 def _check(rc: int, ctx) -> None:
     if rc != GD_OK:
         msg = library().gd_last_error(ctx)
+        raise GdError(rc, msg.decode() if msg else "")
+
+
+def _check_pool(rc: int, pool) -> None:
+    if rc != GD_OK:
+        msg = library().gd_pool_last_error(pool)
         raise GdError(rc, msg.decode() if msg else "")
 
 
@@ -212,6 +232,63 @@ def gd_destroy(ctx) -> None:
 def gd_last_error(ctx=None) -> str:
     msg = library().gd_last_error(ctx)
     return msg.decode() if msg else ""
+
+
+def gd_pool_arena_bytes(max_clusters: int, ns) -> int:
+    arr = (C.c_int64 * max(1, len(ns)))(*[int(v) for v in ns])
+    out = C.c_size_t()
+    _check_pool(library().gd_pool_arena_bytes(int(max_clusters), arr, len(ns), C.byref(out)), None)
+    return int(out.value)
+
+
+def gd_pool_create(params: gd_params, max_clusters: int, arena, stream=None):
+    pool = _VP()
+    rc = library().gd_pool_create(C.byref(pool), C.byref(params), int(max_clusters),
+                                  _ptr(arena, torch.uint8, None, "arena"), arena.numel(), _stream_handle(stream))
+    _check_pool(rc, None)
+    return pool
+
+
+def gd_pool_admit(pool, m, x, v, t_end: float):
+    """Slot of the admitted cluster, or None when no slot or arena room is free."""
+    n = m.shape[0]
+    slot = C.c_int32(-1)
+    rc = library().gd_pool_admit(pool, n, _ptr(m, torch.float64, (n,), "m"), _ptr(x, torch.float64, (n, 3), "x"),
+                                 _ptr(v, torch.float64, (n, 3), "v"), float(t_end), C.byref(slot))
+    if rc == GD_ENOMEM:
+        return None
+    _check_pool(rc, pool)
+    return int(slot.value)
+
+
+def gd_pool_run(pool) -> list:
+    fin = (C.c_int32 * 64)()
+    nf = C.c_int32(0)
+    _check_pool(library().gd_pool_run(pool, fin, C.byref(nf)), pool)
+    return [int(fin[k]) for k in range(nf.value)]
+
+
+def gd_pool_result(pool, slot: int, x=None, v=None) -> dict:
+    st = gd_stats()
+    f = torch.float64
+    _check_pool(library().gd_pool_result(pool, int(slot), _ptr(x, f, None, "x"), _ptr(v, f, None, "v"),
+                                         C.byref(st)), pool)
+    return st.as_dict()
+
+
+def gd_pool_release(pool, slot: int) -> None:
+    _check_pool(library().gd_pool_release(pool, int(slot)), pool)
+
+
+def gd_pool_resident(pool) -> int:
+    c = C.c_int32()
+    _check_pool(library().gd_pool_resident(pool, C.byref(c)), pool)
+    return int(c.value)
+
+
+def gd_pool_destroy(pool) -> None:
+    if pool:
+        library().gd_pool_destroy(pool)
 
 
 class Cluster:

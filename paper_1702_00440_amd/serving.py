@@ -1,0 +1,123 @@
+"""Continuous-batching request loop over a gd_pool (argument marshalling and
+host bookkeeping only; every step of every integration runs in the HIP
+library).
+
+Requests (independent clusters: masses, positions, velocities already on the
+device, and an end time) arrive at given times. The loop admits arrived
+requests in arrival order whenever a pool slot and room in the device arena
+are free (admission by footprint), advances all resident clusters together
+with gd_pool_run, and retires clusters as they finish, recording for each its
+arrival, admission and completion times.
+"""
+from __future__ import annotations
+
+import collections
+import time
+from dataclasses import dataclass, field
+
+import torch
+
+from . import gravidy as g
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float  # seconds after the start of serving
+    m: torch.Tensor
+    x: torch.Tensor
+    v: torch.Tensor
+    t_end: float
+
+
+@dataclass
+class Result:
+    rid: int
+    n: int
+    arrival: float
+    admitted: float
+    done: float
+    stats: dict
+    x: torch.Tensor | None = None
+    v: torch.Tensor | None = None
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+@dataclass
+class PoolServer:
+    params: g.gd_params
+    max_clusters: int
+    arena_bytes: int
+    device: str = "cuda:0"
+    keep_state: bool = False
+    arena: torch.Tensor = field(init=False)
+    pool: object = field(init=False)
+
+    def __post_init__(self):
+        self.arena = torch.empty(self.arena_bytes, dtype=torch.uint8, device=self.device)
+        self.pool = g.gd_pool_create(self.params, self.max_clusters, self.arena)
+
+    def close(self):
+        if self.pool:
+            g.gd_pool_destroy(self.pool)
+            self.pool = None
+
+    def serve(self, requests: list[Request]) -> list[Result]:
+        pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
+        waiting: collections.deque = collections.deque()
+        running: dict[int, tuple[Request, float]] = {}
+        results: list[Result] = []
+        t0 = time.perf_counter()
+        while pending or waiting or running:
+            now = time.perf_counter() - t0
+            while pending and pending[0].arrival <= now:
+                waiting.append(pending.popleft())
+            while waiting:
+                r = waiting[0]
+                slot = g.gd_pool_admit(self.pool, r.m, r.x, r.v, r.t_end)
+                if slot is None:
+                    break
+                waiting.popleft()
+                running[slot] = (r, time.perf_counter() - t0)
+            if running:
+                for slot in g.gd_pool_run(self.pool):
+                    r, t_adm = running.pop(slot)
+                    xo = vo = None
+                    if self.keep_state:
+                        xo = torch.empty_like(r.x)
+                        vo = torch.empty_like(r.v)
+                    st = g.gd_pool_result(self.pool, slot, xo, vo)
+                    g.gd_pool_release(self.pool, slot)
+                    results.append(Result(r.rid, r.m.shape[0], r.arrival, t_adm, time.perf_counter() - t0, st,
+                                          xo, vo))
+            elif pending:
+                time.sleep(max(0.0, min(1e-3, pending[0].arrival - (time.perf_counter() - t0))))
+        return results
+
+
+def serve_sequential(params: g.gd_params, requests: list[Request], device="cuda:0",
+                     keep_state=False) -> list[Result]:
+    """The same requests, one after the other, each with its own context
+    (gd_init, gd_step_to to its end time): the plain baseline."""
+    results = []
+    t0 = time.perf_counter()
+    for r in sorted(requests, key=lambda r: r.arrival):
+        now = time.perf_counter() - t0
+        if r.arrival > now:
+            time.sleep(r.arrival - now)
+        t_adm = time.perf_counter() - t0
+        n = r.m.shape[0]
+        ws = torch.empty(g.gd_workspace_bytes(n, params), dtype=torch.uint8, device=device)
+        ctx = g.gd_init(params, r.m, r.x, r.v, ws)
+        st = g.gd_step_to(ctx, r.t_end)
+        xo = vo = None
+        if keep_state:
+            xo = torch.empty_like(r.x)
+            vo = torch.empty_like(r.v)
+            g.gd_get_state(ctx, xo, vo)
+        g.gd_destroy(ctx)
+        results.append(Result(r.rid, n, r.arrival, t_adm, time.perf_counter() - t0, st, xo, vo))
+    return results

@@ -116,3 +116,14 @@ def test_init_rejects_bad_central_particle():
         p = g.make_params(**kw)
         rc = lib.gd_init(C.byref(ctx), C.byref(p), 16, dummy, dummy, dummy, dummy, 1 << 30, None)
         assert rc == g.GD_EINVAL, kw
+
+
+def test_pool_create_validation_host_only():
+    lib = g.library()
+    pool = C.c_void_p()
+    dummy = C.c_void_p(256)
+    for kw, mc in [(dict(), 0), (dict(), 65), (dict(eps=0.0), 4), (dict(bh_index=1, eps_bh=1e-6), 4)]:
+        p = g.make_params(**kw)
+        rc = lib.gd_pool_create(C.byref(pool), C.byref(p), mc, dummy, 1 << 30, None)
+        assert rc == g.GD_EINVAL, (kw, mc)
+    assert g.gd_pool_arena_bytes(4, [256, 512]) > g.gd_workspace_bytes(256) + g.gd_workspace_bytes(512)
