@@ -73,6 +73,10 @@ def main():
     ap.add_argument("--no-profile", action="store_true", help="skip the force-launch event timing")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES of device memory once (calibrates HBM byte counters)")
+    ap.add_argument("--requests", type=int, default=128, help="serving: number of clusters")
+    ap.add_argument("--rho", type=float, default=1.0,
+                    help="serving: arrival rate as a multiple of the sequential solve rate")
+    ap.add_argument("--max-clusters", type=int, default=64, help="serving: pool slots")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1 "
@@ -96,6 +100,10 @@ def main():
 
     from paper_1702_00440_amd import gravidy as g
     from synth_inputs import WORKLOADS, plummer
+
+    if args.workload == "serving":
+        serving_bench(args)
+        return
 
     w = WORKLOADS[args.workload]
     n, t_end, dt_max = w["n"], w["t_end"], w["dt_max"]
@@ -186,6 +194,85 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     cl.close()
+    print(json.dumps(out), flush=True)
+
+
+def serving_bench(args):
+    """Continuous batching of independent Plummer clusters: N log-uniform in
+    [256, 8192] (seeded), equal masses, eps 1e-4, eta 0.01, each integrated to
+    t = 0.5; Poisson arrivals at rho times the sequential solve rate measured
+    first on the same requests. Reports solves/s and latency percentiles for
+    the pool and for sequential plain solves."""
+    import numpy as np
+    import torch
+
+    from paper_1702_00440_amd import gravidy as g
+    from paper_1702_00440_amd import serving
+    from synth_inputs import plummer
+
+    rng = np.random.default_rng(2024)
+    dev = "cuda:0"
+    t_end = 0.5
+    reqs = []
+    for k in range(args.requests):
+        n = int(round(np.exp(rng.uniform(np.log(256), np.log(8192)))))
+        m, x, v = plummer(n, 1000 + k)
+        reqs.append(serving.Request(k, 0.0, torch.as_tensor(m).to(dev), torch.as_tensor(x).to(dev).contiguous(),
+                                    torch.as_tensor(v).to(dev).contiguous(), t_end))
+    p = g.make_params(eta=0.01, eps=1e-4, dt_max=0.125, dt_min=2.0 ** -22)
+    # warm-up: one small solve each way
+    serving.serve_sequential(p, reqs[:1])
+    # sequential baseline, all requests available at once
+    t0 = time.perf_counter()
+    seq = serving.serve_sequential(p, reqs)
+    seq_wall = time.perf_counter() - t0
+    seq_rate = len(reqs) / seq_wall
+    lam = args.rho * seq_rate
+    arr = np.cumsum(rng.exponential(1.0 / lam, len(reqs)))
+    arr -= arr[0]
+    for r, a in zip(reqs, arr):
+        r.arrival = float(a)
+    seq_lat = [r.latency for r in serving.serve_sequential(p, reqs)] if args.rho > 0 else []
+    nmax = max(r.m.shape[0] for r in reqs)
+    arena_bytes = g.gd_pool_arena_bytes(args.max_clusters, [nmax] * args.max_clusters)
+    srv = serving.PoolServer(p, args.max_clusters, arena_bytes)
+    srv.serve(reqs[:2])  # warm-up (graph capture)
+    # capacity: every request available at t = 0
+    burst = [serving.Request(r.rid, 0.0, r.m, r.x, r.v, r.t_end) for r in reqs]
+    t0 = time.perf_counter()
+    res_burst = srv.serve(burst)
+    wall = time.perf_counter() - t0
+    # latency under Poisson arrivals
+    res = srv.serve(reqs)
+    srv.close()
+    lat = np.array([r.latency for r in res])
+    pairs = sum(r.stats["pair_interactions"] for r in res_burst)
+    out = {
+        "metric": "serving solves/s",
+        "value": len(res) / wall,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 1,
+        "ms_per_step": wall * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "serving_plummer_n256-8192_t0.5", "requests": len(reqs), "rho": args.rho,
+                   "arrival_rate_per_s": lam, "max_clusters": args.max_clusters, "eps": 1e-4, "eta": 0.01},
+        "value_kind": "capacity: all requests queued at t=0",
+        "latency_p50_s": float(np.percentile(lat, 50)),
+        "latency_p99_s": float(np.percentile(lat, 99)),
+        "latency_kind": f"Poisson arrivals at rho={args.rho} x the sequential solve rate",
+        "pairs_per_s": pairs / wall,
+        "sequential": {
+            "solves_per_s": seq_rate,
+            "latency_p50_s": float(np.percentile(seq_lat, 50)) if seq_lat else None,
+            "latency_p99_s": float(np.percentile(seq_lat, 99)) if seq_lat else None,
+        },
+    }
     print(json.dumps(out), flush=True)
 
 

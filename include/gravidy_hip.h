@@ -185,6 +185,25 @@ gd_status gd_step_to(gd_ctx* c, double t_end, gd_stats* st);
 gd_status gd_energy(gd_ctx* c, double* ekin, double* epot, double* epot_unsoft);
 
 /*
+ * Diagnostics of the synchronised state (Sec. 4.2):
+ *   - Lagrange radii: for each fraction f in fractions[0..n_frac) (host, in
+ *     (0, 1], at most 32), the distance from the centre of mass of the first
+ *     particle, in ascending distance (ties by index), at which the
+ *     cumulative mass reaches f times the total mass; written to radii
+ *     (host) in the same order;
+ *   - *t_rh (host, may be NULL): half-mass relaxation time, Eq. (5) with G = 1,
+ *     0.138 (N r_h^3 / m)^(1/2) / ln(0.1 N), m the mean mass, r_h the radius
+ *     at f = 1/2 (also returned in *r_half, may be NULL);
+ *   - level_counts (host, may be NULL): particles per block-step level,
+ *     level k meaning dt = dt_max / 2^k, for k < n_levels (zero beyond
+ *     log2(dt_max / dt_min)).
+ * Synchronises. Errors: GD_ESTATE unless synchronised (as gd_energy),
+ * GD_EINVAL for bad fractions or buffers, GD_EHIP.
+ */
+gd_status gd_diagnostics(gd_ctx* c, const double* fractions, int32_t n_frac, double* radii,
+                         double* t_rh, double* r_half, int64_t* level_counts, int32_t n_levels);
+
+/*
  * Copy the particle state out: x, v, a (acceleration), jerk as device
  * (n, 3) arrays at each particle's own time; t_i and dt_i as device double[n];
  * *t_now (host) the current block time. Any pointer may be NULL.

@@ -292,3 +292,38 @@ class State:
     def energy(self):
         ek, ep = energy(self.m, self.x, self.v, self.eps, eps_bh=self.eps_bh, bh=self.bh)
         return ek + ep
+
+
+def lagrange_radii(m, x, fractions):
+    """Lagrange radii (the paper's Sec. 4.2: radii of the spheres that hold
+    given mass fractions), about the centre of mass: particles in ascending
+    distance (ties by index), cumulative mass in that order; the radius for
+    fraction f is the distance of the first particle at which the cumulative
+    mass reaches f times the total mass. Plain numpy."""
+    m = np.asarray(m, dtype=np.float64)
+    x = np.asarray(x, dtype=np.float64).reshape(-1, 3)
+    mt = 0.0
+    for mi in m:
+        mt += mi
+    com = np.zeros(3)
+    for d in range(3):
+        acc = 0.0
+        for mi, xi in zip(m, x[:, d]):
+            acc += mi * xi
+        com[d] = acc / mt
+    r2 = ((x - com) ** 2).sum(axis=1)
+    order = np.argsort(r2, kind="stable")
+    cum = np.cumsum(m[order])
+    out = []
+    for f in fractions:
+        k = int(np.searchsorted(cum, f * mt, side="left"))
+        k = min(k, len(m) - 1)
+        out.append(float(np.sqrt(r2[order[k]])))
+    return np.array(out)
+
+
+def half_mass_relaxation_time(n, total_mass, r_h):
+    """Half-mass relaxation time, Eq. (5) with G = 1:
+    0.138 (N r_h^3 / m)^(1/2) / ln(0.1 N), m the mean particle mass."""
+    mean_m = total_mass / n
+    return 0.138 * math.sqrt(n * r_h ** 3 / mean_m) / math.log(0.1 * n)

@@ -494,6 +494,37 @@ gd_status gd_energy(gd_ctx* c, double* ekin, double* epot, double* epot_unsoft) 
   return GD_OK;
 }
 
+gd_status gd_diagnostics(gd_ctx* c, const double* fractions, int32_t n_frac, double* radii,
+                         double* t_rh, double* r_half, int64_t* level_counts, int32_t n_levels) {
+  if (!c) return GD_EINVAL;
+  if (n_frac < 0 || n_frac > kMaxDiagFractions || (n_frac > 0 && (!fractions || !radii)) || n_levels < 0 ||
+      (n_levels > 0 && !level_counts))
+    return c->fail(GD_EINVAL, "bad fractions or level buffer");
+  if (!c->synced || c->phase != kIdle)
+    return c->fail(GD_ESTATE, "particles are not synchronised (use gd_step_to to a multiple of dt_max)");
+  // Ascending fractions for the single pass; results are returned in the
+  // caller's order.
+  std::vector<std::pair<double, int>> fr;
+  for (int q = 0; q < n_frac; ++q) {
+    if (!(fractions[q] > 0.0 && fractions[q] <= 1.0)) return c->fail(GD_EINVAL, "fractions must be in (0, 1]");
+    fr.push_back({fractions[q], q});
+  }
+  std::sort(fr.begin(), fr.end());
+  double sorted[kMaxDiagFractions];
+  for (int q = 0; q < n_frac; ++q) sorted[q] = fr[q].first;
+  GD_TRY(c->hip(launch_diagnostics(c->d, c->c, sorted, n_frac, c->d.ebuf, c->stream), "diagnostics"));
+  double out[kMaxDiagFractions + 2];
+  GD_TRY(c->hip(hipMemcpyAsync(out, c->d.ebuf, sizeof(double) * (n_frac + 2), hipMemcpyDeviceToHost,
+                               c->stream),
+                "read diagnostics"));
+  GD_TRY(read_sched(c));  // synchronises; also brings the level histogram
+  for (int q = 0; q < n_frac; ++q) radii[fr[q].second] = out[q];
+  if (t_rh) *t_rh = out[n_frac];
+  if (r_half) *r_half = out[n_frac + 1];
+  for (int k = 0; k < n_levels; ++k) level_counts[k] = k <= c->c.kmax ? c->h_sc->hist[k] : 0;
+  return GD_OK;
+}
+
 gd_status gd_get_state(gd_ctx* c, double* x, double* v, double* a, double* jerk, double* t_i,
                        double* dt_i, double* t_now) {
   if (!c) return GD_EINVAL;

@@ -34,6 +34,9 @@ constexpr int kEnergyGrid = 1024;
 // Maximum block-step level (dt = dt_max / 2^level).
 constexpr int kMaxLevels = 41;
 
+// Mass fractions one diagnostics call can take.
+constexpr int kMaxDiagFractions = 32;
+
 // Predictor modes.
 enum : int { kPredAuto = 0, kPredAll = 1, kPredExplicit = 2 };
 
@@ -102,7 +105,9 @@ inline long long partial_rows(long long n) {
   const long long it_max = (long long)(kBlock >> kMinLj) * kIPerLane;
   const long long by_items = n + it_max + (long long)kTargetItems * it_max;
   const long long by_slices = ((n + kMinSlice - 1) / kMinSlice) * n;
-  return by_items < by_slices ? by_items : by_slices;
+  const long long rows = by_items < by_slices ? by_items : by_slices;
+  // Also scratch of the diagnostics sort: 1.5 * 2n + n / 64 + 8 doubles.
+  return rows > n + 16 ? rows : n + 16;
 }
 
 // Energy decomposition: items are (i tile of kBlock, j slice).
@@ -203,6 +208,10 @@ struct PoolStatus {
 };
 
 hipError_t launch_pool_step(const PoolSlot* slots, const PoolTable* tab, hipStream_t s);
+// Lagrange radii of the ascending fractions frac[0..n_frac) into out[0..n_frac),
+// Eq. (5) into out[n_frac], the half-mass radius into out[n_frac + 1].
+hipError_t launch_diagnostics(const Dev& d, const Consts& c, const double* frac, int n_frac,
+                              double* out, hipStream_t s);
 hipError_t launch_pool_status(const PoolSlot* slots, const PoolTable* tab, PoolStatus* out,
                               hipStream_t s);
 

@@ -1012,6 +1012,126 @@ __global__ void k_pool_status(const PoolSlot* __restrict__ slots, const PoolTabl
 }
 
 // ---------------------------------------------------------------------------
+// Diagnostics: Lagrange radii and half-mass relaxation time (Sec. 4.2, Eq. (5))
+// ---------------------------------------------------------------------------
+//
+// Lagrange radius of mass fraction f: about the centre of mass, the distance
+// of the first particle (in ascending distance, ties by index) at which the
+// cumulative mass reaches f times the total. The distances are sorted on the
+// device (bitonic network over the bit patterns of r^2, which order like the
+// values for r^2 >= 0) and the masses are accumulated in sorted order by one
+// lane, so the cumulative sums are the plain sequential ones.
+
+struct DiagArgs {
+  int n_frac;
+  double frac[kMaxDiagFractions];  // ascending
+};
+
+// Per-workgroup partial sums of m, m x, m y, m z (fixed-order tree).
+__global__ __launch_bounds__(kBlock) void k_diag_com(int n, const double* __restrict__ m,
+                                                     const double* __restrict__ x,
+                                                     const double* __restrict__ y,
+                                                     const double* __restrict__ z,
+                                                     double* __restrict__ wg_out) {
+  __shared__ double red[4][kBlock];
+  const int tid = threadIdx.x;
+  const int i = blockIdx.x * kBlock + tid;
+  double v[4] = {0, 0, 0, 0};
+  if (i < n) {
+    v[0] = m[i];
+    v[1] = m[i] * x[i];
+    v[2] = m[i] * y[i];
+    v[3] = m[i] * z[i];
+  }
+  for (int q = 0; q < 4; ++q) red[q][tid] = v[q];
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (tid < w)
+      for (int q = 0; q < 4; ++q) red[q][tid] += red[q][tid + w];
+    __syncthreads();
+  }
+  if (tid == 0)
+    for (int q = 0; q < 4; ++q) wg_out[4 * blockIdx.x + q] = red[q][0];
+}
+
+// Sort keys: bit pattern of r^2 about the centre of mass (padding: max key).
+__global__ __launch_bounds__(kBlock) void k_diag_keys(int n, int npow2, int nwg,
+                                                      const double* __restrict__ wg,
+                                                      const double* __restrict__ x,
+                                                      const double* __restrict__ y,
+                                                      const double* __restrict__ z,
+                                                      unsigned long long* __restrict__ key,
+                                                      int* __restrict__ idx) {
+  __shared__ double com[4];
+  const int tid = threadIdx.x;
+  if (tid < 4) {
+    double acc = 0.0;
+    for (int b = 0; b < nwg; ++b) acc += wg[4 * b + tid];
+    com[tid] = acc;
+  }
+  __syncthreads();
+  const int i = blockIdx.x * kBlock + tid;
+  if (i >= npow2) return;
+  if (i < n) {
+    const double dx = x[i] - com[1] / com[0], dy = y[i] - com[2] / com[0], dz = z[i] - com[3] / com[0];
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    key[i] = (unsigned long long)__double_as_longlong(r2);
+  } else {
+    key[i] = ~0ULL;
+  }
+  idx[i] = i;
+}
+
+// One compare-exchange stage of the bitonic network on (key, index) pairs.
+__global__ __launch_bounds__(kBlock) void k_bitonic(int npow2, int j, int k,
+                                                    unsigned long long* __restrict__ key,
+                                                    int* __restrict__ idx) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= npow2) return;
+  const int l = i ^ j;
+  if (l <= i) return;
+  const bool up = (i & k) == 0;
+  const unsigned long long ki = key[i], kl = key[l];
+  const int ii = idx[i], il = idx[l];
+  const bool greater = ki > kl || (ki == kl && ii > il);
+  if (greater == up) {
+    key[i] = kl;
+    key[l] = ki;
+    idx[i] = il;
+    idx[l] = ii;
+  }
+}
+
+// One lane: total mass in index order, cumulative mass in sorted order, the
+// radius for each fraction, and Eq. (5) for the half-mass radius
+// (out[n_frac]; out[n_frac + 1] is the radius at f = 1/2).
+__global__ void k_diag_scan(int n, const double* __restrict__ m,
+                            const unsigned long long* __restrict__ key, const int* __restrict__ idx,
+                            DiagArgs a, double* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double mt = 0.0;
+  for (int i = 0; i < n; ++i) mt += m[i];
+  double cum = 0.0;
+  int f = 0;
+  double rh = 0.0;
+  bool rh_set = false;
+  for (int r = 0; r < n && (f < a.n_frac || !rh_set); ++r) {
+    cum += m[idx[r]];
+    const double rad = sqrt(__longlong_as_double((long long)key[r]));
+    while (f < a.n_frac && cum >= a.frac[f] * mt) out[f++] = rad;
+    if (!rh_set && cum >= 0.5 * mt) {
+      rh = rad;
+      rh_set = true;
+    }
+  }
+  const double last = sqrt(__longlong_as_double((long long)key[n - 1]));
+  while (f < a.n_frac) out[f++] = last;
+  if (!rh_set) rh = last;
+  out[a.n_frac + 1] = rh;
+  out[a.n_frac] = 0.138 * sqrt((double)n * rh * rh * rh / (mt / n)) / log(0.1 * n);
+}
+
+// ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
 
@@ -1107,6 +1227,35 @@ hipError_t launch_set_state(const Dev& d, const Consts& c, const double* x, cons
   hipLaunchKernelGGL(k_set_state, dim3(grid_for(c.n)), dim3(kBlock), 0, s, d.sc, c.n, c.kmax,
                      c.dt_min, t_now, x, v, a, jerk, t_i, dt_i, d.x, d.y, d.z, d.vx, d.vy, d.vz,
                      d.ax, d.ay, d.az, d.jx, d.jy, d.jz, d.tick, d.lev);
+  return hipGetLastError();
+}
+
+hipError_t launch_diagnostics(const Dev& d, const Consts& c, const double* frac, int n_frac,
+                              double* out, hipStream_t s) {
+  const int n = c.n;
+  int npow2 = 1;
+  while (npow2 < n) npow2 <<= 1;
+  const int nwg = grid_for(n);
+  // Scratch in the partial-force buffer (unused between block steps): the
+  // workgroup sums, then keys and indices.
+  double* wg = d.part;
+  unsigned long long* key = (unsigned long long*)(d.part + 4 * (size_t)nwg + 8);
+  int* idx = (int*)(key + npow2);
+  hipLaunchKernelGGL(k_diag_com, dim3(nwg), dim3(kBlock), 0, s, n, d.m, d.x, d.y, d.z, wg);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_diag_keys, dim3(grid_for(npow2)), dim3(kBlock), 0, s, n, npow2, nwg, wg, d.x,
+                     d.y, d.z, key, idx);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  for (int k = 2; k <= npow2; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      hipLaunchKernelGGL(k_bitonic, dim3(grid_for(npow2)), dim3(kBlock), 0, s, npow2, j, k, key, idx);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+  DiagArgs a{};
+  a.n_frac = n_frac;
+  for (int q = 0; q < n_frac; ++q) a.frac[q] = frac[q];
+  hipLaunchKernelGGL(k_diag_scan, dim3(1), dim3(64), 0, s, n, d.m, key, idx, a, out);
   return hipGetLastError();
 }
 

@@ -71,6 +71,9 @@ def library():
     lib.gd_get_state.argtypes = [_VP, _VP, _VP, _VP, _VP, _VP, _VP, C.POINTER(C.c_double)]
     lib.gd_set_state.argtypes = [_VP, _VP, _VP, _VP, _VP, _VP, _VP, C.c_double]
     lib.gd_stats_get.argtypes = [_VP, C.POINTER(gd_stats)]
+    lib.gd_diagnostics.argtypes = [_VP, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_double),
+                                   C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(i64), C.c_int32]
+    lib.gd_diagnostics.restype = st
     for name in ["gd_workspace_bytes", "gd_init", "gd_reinit", "gd_profile_force", "gd_profile_get", "gd_predict", "gd_force", "gd_active", "gd_correct",
                  "gd_step_to", "gd_energy", "gd_get_state", "gd_set_state", "gd_stats_get"]:
         getattr(lib, name).restype = st
@@ -216,6 +219,19 @@ def gd_set_state(ctx, x, v, a, jerk, t_i, dt_i, t_now: float) -> None:
     _check(library().gd_set_state(ctx, _ptr(x, f, None, "x"), _ptr(v, f, None, "v"), _ptr(a, f, None, "a"),
                                   _ptr(jerk, f, None, "jerk"), _ptr(t_i, f, None, "t_i"),
                                   _ptr(dt_i, f, None, "dt_i"), float(t_now)), ctx)
+
+
+def gd_diagnostics(ctx, fractions=(0.01, 0.05, 0.1, 0.25, 0.5, 0.75, 0.9), n_levels=41) -> dict:
+    """Lagrange radii at the given mass fractions, half-mass relaxation time
+    (Eq. 5) and the particles per block-step level, from the device."""
+    nf = len(fractions)
+    fr = (C.c_double * max(1, nf))(*[float(f) for f in fractions])
+    radii = (C.c_double * max(1, nf))()
+    t_rh, r_half = C.c_double(), C.c_double()
+    levels = (C.c_int64 * max(1, n_levels))()
+    _check(library().gd_diagnostics(ctx, fr, nf, radii, C.byref(t_rh), C.byref(r_half), levels, n_levels), ctx)
+    return {"fractions": list(fractions), "radii": [radii[k] for k in range(nf)], "t_rh": t_rh.value,
+            "r_half": r_half.value, "levels": [int(levels[k]) for k in range(n_levels)]}
 
 
 def gd_stats_get(ctx) -> dict:

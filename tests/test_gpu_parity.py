@@ -261,3 +261,27 @@ def test_reinit_matches_init_and_profiles_force():
         np.testing.assert_array_equal(host(u), host(w))
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("n", [2, 3, 1000, 4096])
+def test_diagnostics_against_oracle(n):
+    """Lagrange radii, Eq. (5) and the level histogram of the synchronised
+    state, at t = 0 and after a run to t = 1/8."""
+    m, x, v = plummer(n, 9)
+    cl = g.Cluster(m, x, v, eta=ETA, eps=EPS, device=DEV)
+    fr = [0.9, 0.01, 0.1, 0.5, 0.25, 1.0]
+    for t in [0.0, 0.125]:
+        if t > 0:
+            g.gd_step_to(cl.ctx, t)
+        xs, _, _, _, _, dt_i, _ = cl.state()
+        d = g.gd_diagnostics(cl.ctx, fr)
+        ref = oracle.lagrange_radii(m, host(xs), fr)
+        np.testing.assert_allclose(d["radii"], ref, rtol=1e-12)
+        rh = oracle.lagrange_radii(m, host(xs), [0.5])[0]
+        assert d["r_half"] == pytest.approx(rh, rel=1e-12)
+        assert d["t_rh"] == pytest.approx(oracle.half_mass_relaxation_time(n, m.sum(), rh), rel=1e-12)
+        levels = np.round(np.log2(DTMAX / host(dt_i))).astype(int)
+        np.testing.assert_array_equal(d["levels"][:20], np.bincount(levels, minlength=20)[:20])
+    with pytest.raises(g.GdError):
+        g.gd_diagnostics(cl.ctx, [1.5])
+    cl.close()

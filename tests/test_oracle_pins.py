@@ -478,3 +478,42 @@ def test_energy_error_grows_with_eta():
         rows = s.run(0.5)
         out.append(rows[:, 5].max())
     assert out[1] > 5 * out[0], out
+
+
+# --------------------------------------------------------------------------
+# Diagnostics (Lagrange radii, half-mass relaxation time)
+# --------------------------------------------------------------------------
+
+def test_lagrange_radii_shells():
+    """Particles on concentric shells of known radii, symmetric about the
+    origin: each fraction's radius is the shell where the enclosed mass first
+    reaches it."""
+    dirs = np.array([[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]], dtype=float)
+    radii = [0.5, 1.0, 2.0, 4.0]
+    x = np.concatenate([r * dirs for r in radii])
+    m = np.full(len(x), 1.0 / len(x))
+    got = oracle.lagrange_radii(m, x, [0.1, 0.25, 0.26, 0.5, 0.75, 0.9, 1.0])
+    np.testing.assert_allclose(got, [0.5, 0.5, 1.0, 1.0, 2.0, 4.0, 4.0], rtol=1e-15)
+
+
+def test_lagrange_radii_plummer_model():
+    """A large Plummer sample in Henon units: radii of mass fraction f follow
+    the model's r_f = b (f^(-2/3) - 1)^(-1/2), b = 3 pi / 16, within sampling
+    noise."""
+    m, x, v = plummer(16384, 5)
+    fr = np.array([0.1, 0.25, 0.5, 0.75, 0.9])
+    got = oracle.lagrange_radii(m, x, fr)
+    b = 3 * math.pi / 16
+    model = b / np.sqrt(fr ** (-2.0 / 3.0) - 1.0)
+    np.testing.assert_allclose(got, model, rtol=0.04)
+
+
+def test_half_mass_relaxation_time_values():
+    """Eq. (5): the paper quotes T_rh = 112.186 NBU for its N = 8192 runs
+    (Sec. 4.2), which with m = 1/N and ln(0.1 N) implies r_h ~ 0.78, close to
+    the Plummer half-mass radius 0.769 of Henon units."""
+    t = oracle.half_mass_relaxation_time(8192, 1.0, 0.7690)
+    assert 105 < t < 115
+    # scaling: t_rh ~ r_h^(3/2) at fixed N
+    assert oracle.half_mass_relaxation_time(1000, 1.0, 2.0) / oracle.half_mass_relaxation_time(1000, 1.0, 1.0) \
+        == pytest.approx(2 ** 1.5, rel=1e-14)
