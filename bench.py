@@ -33,6 +33,37 @@ if ROOT not in sys.path:
 
 FLOPS_PER_PAIR = 60
 PEAK_FP64_VECTOR_TFLOPS = 78.6
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_force_plummer_n16384_traffic.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1702_00440_amd", "csrc", f)
+                  for f in ("gd_kernels.hip", "gd_internal.h")]
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
+def force_traffic(workload):
+    """HBM bytes per force launch from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's reading), or None when
+    there is none for this workload or the kernel sources changed since the
+    counters were taken."""
+    if workload != "plummer_n16384" or not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    fields = {}
+    for line in open(TRAFFIC_PROFILE):
+        if ":" in line and line.startswith("- `"):
+            k, v = line[3:].split("`", 1)[0].split(":", 1)
+            fields[k.strip()] = v.strip()
+    if fields.get("kernel_sources_sha256") != kernel_sources_sha256():
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(w, seconds):
@@ -71,6 +102,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the force-launch event timing")
+    ap.add_argument("--kernel-hash", action="store_true",
+                    help="print the hash of the kernel sources that a counter summary is tied to")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES of device memory once (calibrates HBM byte counters)")
     ap.add_argument("--requests", type=int, default=128, help="serving: number of clusters")
@@ -78,6 +111,9 @@ def main():
                     help="serving: arrival rate as a multiple of the sequential solve rate")
     ap.add_argument("--max-clusters", type=int, default=64, help="serving: pool slots")
     args = ap.parse_args()
+    if args.kernel_hash:
+        print(kernel_sources_sha256())
+        return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1 "
               "(the multi-GPU split is described, not built).", file=sys.stderr)
@@ -184,7 +220,8 @@ def main():
             "peak": PEAK_FP64_VECTOR_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64_VECTOR_TFLOPS,
-            "traffic": None,
+            "traffic": force_traffic(args.workload),
+            "traffic_unit": "HBM bytes per launch",
             "kernel": "k_force<false> (FP64 acc+jerk)",
             "launches": prof["launches"],
             "avg_launch_us": avg_s * 1e6,

@@ -163,31 +163,31 @@ __device__ __forceinline__ void force_body(const Dev& d, const Consts& c, int bl
       A[q] = Acc6{0, 0, 0, 0, 0, 0};
     }
 
-    // Prefetch of the first tile.
+    // Tile loads and LDS stores are lane-uniform (indices clamped into the
+    // slice, lanes past its end store a duplicate that is never read): the
+    // i loads above are then drained on every path before the first tile,
+    // and the inner loop does not wait on the prefetch of the next tile.
+    static_assert(kTileJ == kBlock, "one j per thread per tile");
     double rx = 0, ry = 0, rz = 0, rvx = 0, rvy = 0, rvz = 0, rm = 0;
-    if (j0 < j1 && tid < min(kTileJ, j1 - j0)) {
-      const int j = j0 + tid;
+    auto load_tile = [&](int base) {
+      const int j = min(base + tid, j1 - 1);
       rx = px[j]; ry = py[j]; rz = pz[j];
       rvx = pvx[j]; rvy = pvy[j]; rvz = pvz[j];
       rm = pm[j];
-    }
+    };
+    if (j0 < j1) load_tile(j0);
     for (int jt = j0; jt < j1; jt += kTileJ) {
       const int cnt = min(kTileJ, j1 - jt);
       __syncthreads();
-      if (tid < cnt) {
-        sj[0][tid] = rx; sj[1][tid] = ry; sj[2][tid] = rz;
-        sj[3][tid] = rvx; sj[4][tid] = rvy; sj[5][tid] = rvz;
-        sj[6][tid] = rm;
-      }
+      sj[0][tid] = rx; sj[1][tid] = ry; sj[2][tid] = rz;
+      sj[3][tid] = rvx; sj[4][tid] = rvy; sj[5][tid] = rvz;
+      sj[6][tid] = rm;
       __syncthreads();
-      const int nxt = jt + kTileJ;
-      if (nxt < j1 && tid < min(kTileJ, j1 - nxt)) {
-        const int j = nxt + tid;
-        rx = px[j]; ry = py[j]; rz = pz[j];
-        rvx = pvx[j]; rvy = pvy[j]; rvz = pvz[j];
-        rm = pm[j];
-      }
-      for (int k = jsub; k < cnt; k += LJ) {
+      if (jt + kTileJ < j1) load_tile(jt + kTileJ);
+      // Uniform trip count over whole groups of LJ j (scalar loop control,
+      // no per-lane exit masks), then at most one partial group.
+      const int full = cnt & ~(LJ - 1);
+      auto pairs_with = [&](int k) {
         const double xj = sj[0][k], yj = sj[1][k], zj = sj[2][k];
         const double vxj = sj[3][k], vyj = sj[4][k], vzj = sj[5][k];
         const double mj = sj[6][k];
@@ -204,7 +204,10 @@ __device__ __forceinline__ void force_body(const Dev& d, const Consts& c, int bl
                       e2i[q], A[q]);
           }
         }
-      }
+      };
+#pragma unroll 2
+      for (int kk = 0; kk < full; kk += LJ) pairs_with(kk + jsub);
+      if (full + jsub < cnt) pairs_with(full + jsub);
     }
 
     // Butterfly over the LJ lanes that share an i (consecutive lanes).
