@@ -34,8 +34,9 @@ if ROOT not in sys.path:
 FLOPS_PER_PAIR = 60
 PEAK_FP64_VECTOR_TFLOPS = 78.6
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_force_plummer_n16384_traffic.md")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_1702_00440_amd", "csrc", f)
-                  for f in ("gd_kernels.hip", "gd_internal.h")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1702_00440_amd", "csrc", "gd_kernels.hip"),
+                  os.path.join(ROOT, "paper_1702_00440_amd", "csrc", "gd_internal.h"),
+                  os.path.join(ROOT, "paper_1702_00440_amd", "build.py")]
 
 
 def kernel_sources_sha256():
