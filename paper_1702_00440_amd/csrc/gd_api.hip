@@ -58,7 +58,7 @@ Layout make_layout(long long n) {
   for (int d = 0; d < 3; ++d) L.p[d] = take(nd);
   for (int d = 0; d < 3; ++d) L.pv[d] = take(nd);
   L.tick = take(sizeof(long long) * (size_t)n);
-  L.lev = take(sizeof(int) * (size_t)n);
+  L.lev = take((size_t)n);
   L.active = take(sizeof(int) * (size_t)n);
   for (int d = 0; d < 3; ++d) L.ip[d] = take(nd);
   for (int d = 0; d < 3; ++d) L.ipv[d] = take(nd);
@@ -94,7 +94,7 @@ Dev carve(void* workspace, const Layout& L) {
     *pvs[k] = (double*)(w + L.pv[k]);
   }
   d.tick = (long long*)(w + L.tick);
-  d.lev = (int*)(w + L.lev);
+  d.lev = (unsigned char*)(w + L.lev);
   d.active = (int*)(w + L.active);
   double** is[3] = {&d.ix, &d.iy, &d.iz};
   double** ivs[3] = {&d.ivx, &d.ivy, &d.ivz};

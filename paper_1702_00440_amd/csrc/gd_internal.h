@@ -69,32 +69,38 @@ struct Sched {
 // The plan depends only on (n_act, n). The kernel that fixes n_act for a
 // step (predictor, or the explicit index list) stores it in the Sched record,
 // and the force kernel and every slice reduction read that one copy.
-__host__ __device__ inline Plan make_plan(int n_act, int n) {
-  Plan p;
+// The decomposition with LJ = 2^lj lanes per i; *stop tells whether make_plan
+// takes it (enough items, or the last candidate).
+__host__ __device__ inline Plan plan_for_lj(int n_act, int n, int lj, bool* stop) {
   int max_s = (n + kMinSlice - 1) / kMinSlice;
   if (max_s < 1) max_s = 1;
-  int lj = kMinLj;
-  for (;;) {
-    int it = (kBlock >> lj) * kIPerLane;
-    int nit = (n_act + it - 1) / it;
-    if (nit < 1) nit = 1;
-    int s = kTargetItems / nit;
-    if (s >= 8) s &= ~7;  // slice index then follows blockIdx % 8, i.e. the XCD
-    if (s > max_s) s = max_s;
-    if (s < 1) s = 1;
-    int len = (n + s - 1) / s;
-    bool enough = nit * s >= kTargetItems;
-    bool last = lj == 6 || (len >> (lj + 1)) < kMinJPerLane;
-    if (enough || last) {
-      p.lj = lj;
-      p.it = it;
-      p.nit = nit;
-      p.s = s;
-      p.len = len;
-      p.items = nit * s;
-      return p;
-    }
-    ++lj;
+  const int it = (kBlock >> lj) * kIPerLane;
+  int nit = (n_act + it - 1) / it;
+  if (nit < 1) nit = 1;
+  int s = kTargetItems / nit;
+  if (s >= 8) s &= ~7;  // slice index then follows blockIdx % 8, i.e. the XCD
+  if (s > max_s) s = max_s;
+  if (s < 1) s = 1;
+  const int len = (n + s - 1) / s;
+  const bool enough = nit * s >= kTargetItems;
+  const bool last = lj == 6 || (len >> (lj + 1)) < kMinJPerLane;
+  *stop = enough || last;
+  Plan p;
+  p.lj = lj;
+  p.it = it;
+  p.nit = nit;
+  p.s = s;
+  p.len = len;
+  p.items = nit * s;
+  return p;
+}
+
+// The first lj from kMinLj up that gives enough items (or the last one).
+__host__ __device__ inline Plan make_plan(int n_act, int n) {
+  for (int lj = kMinLj;; ++lj) {
+    bool stop = false;
+    const Plan p = plan_for_lj(n_act, n, lj, &stop);
+    if (stop) return p;
   }
 }
 
@@ -136,7 +142,7 @@ struct Dev {
   double *ax, *ay, *az, *jx, *jy, *jz;     // acceleration, jerk at t_i
   double *px, *py, *pz, *pvx, *pvy, *pvz;  // predicted j stream
   long long* tick;                         // t_i in dt_min ticks
-  int* lev;                                // dt_i = dt_max / 2^lev
+  unsigned char* lev;                      // dt_i = dt_max / 2^lev
   int* active;                             // active list (positions 0..n_act-1)
   double *ix, *iy, *iz, *ivx, *ivy, *ivz;  // predicted state of the active list, by position
   double *iax, *iay, *iaz, *ijx, *ijy, *ijz;  // a, jerk at t_i of the active list, by position

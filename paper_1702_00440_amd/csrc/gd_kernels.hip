@@ -86,6 +86,83 @@ __device__ __forceinline__ double norm3(double a, double b, double c) {
   return sqrt(a * a + b * b + c * c);
 }
 
+// Predicted position and velocity (Sec. 2.1): the Taylor series through the
+// jerk over dt, as x + dt (v + dt/2 (a + dt/3 jerk)) and v + dt (a + dt/2 jerk).
+// Every kernel that predicts uses this one sequence of operations.
+__device__ __forceinline__ void taylor6(double dt, double x0, double y0, double z0, double vx0,
+                                        double vy0, double vz0, double ax0, double ay0, double az0,
+                                        double jx0, double jy0, double jz0, double o[6]) {
+  const double h2 = 0.5 * dt, h3 = dt * (1.0 / 3.0);
+  o[0] = fma(dt, fma(h2, fma(h3, jx0, ax0), vx0), x0);
+  o[1] = fma(dt, fma(h2, fma(h3, jy0, ay0), vy0), y0);
+  o[2] = fma(dt, fma(h2, fma(h3, jz0, az0), vz0), z0);
+  o[3] = fma(dt, fma(h2, jx0, ax0), vx0);
+  o[4] = fma(dt, fma(h2, jy0, ay0), vy0);
+  o[5] = fma(dt, fma(h2, jz0, az0), vz0);
+}
+
+struct NextStep {
+  long long t_next;
+  int kthr, n_act, done;
+};
+
+// Sum over a wave of values in [0, 2^nbits), by bit slices: a ballot and a
+// population count per bit, no lane-to-lane data movement.
+__device__ __forceinline__ int wave_sum_bits(int v, int nbits) {
+  int s = 0;
+  for (int b = 0; b < nbits; ++b) s += __popcll(__ballot((v >> b) & 1)) << b;
+  return s;
+}
+
+// Bits needed for counts up to n.
+__host__ __device__ inline int count_bits(int n) {
+  int b = 1;
+  while ((1LL << b) <= n) ++b;
+  return b;
+}
+
+// The next block step from the level histogram (Sec. 2.4 steps 5-6),
+// evaluated by one whole wave; lane l holds h = hist[l] (0 for l > kmax).
+// Every particle of level k sits on a multiple of its step 2^(kmax-k) ticks,
+// so the next block time is the next multiple of the smallest step present
+// (the finest occupied level is the highest set bit of a ballot), the active
+// particles are those with level >= kmax - ctz(t_next), and their number is
+// the histogram's tail sum (a bit-sliced wave sum). Every lane returns the
+// same result.
+__device__ __forceinline__ NextStep next_step_wave(int h, int lane, int kmax, long long t_now,
+                                                   long long t_end, int nbits) {
+  const unsigned long long occ = __ballot(h > 0);
+  const int kmx = occ ? 63 - __clzll((long long)occ) : 0;
+  const int sh = kmax - kmx;
+  NextStep r;
+  r.t_next = ((t_now >> sh) + 1) << sh;
+  const int tz = __builtin_ctzll((unsigned long long)r.t_next);
+  r.kthr = max(0, kmax - tz);
+  r.n_act = wave_sum_bits(lane >= r.kthr ? h : 0, nbits);
+  r.done = r.t_next > t_end;
+  return r;
+}
+
+// make_plan evaluated by one whole wave: lane l tries lj = kMinLj + l with
+// the same plan_for_lj, and the first lane that stops wins (its plan read
+// back lane by lane), so every lane returns make_plan(n_act, n).
+__device__ __forceinline__ Plan make_plan_wave(int n_act, int n, int lane) {
+  const int lj = kMinLj + lane;
+  bool stop = false;
+  Plan p{};
+  if (lj <= 6) p = plan_for_lj(n_act, n, lj, &stop);
+  const unsigned long long st = __ballot(stop);
+  const int first = __ffsll((long long)st) - 1;
+  Plan q;
+  q.lj = __builtin_amdgcn_readlane(p.lj, first);
+  q.it = __builtin_amdgcn_readlane(p.it, first);
+  q.nit = __builtin_amdgcn_readlane(p.nit, first);
+  q.s = __builtin_amdgcn_readlane(p.s, first);
+  q.len = __builtin_amdgcn_readlane(p.len, first);
+  q.items = __builtin_amdgcn_readlane(p.items, first);
+  return q;
+}
+
 // ---------------------------------------------------------------------------
 // Force kernel: O(N_act * N) acceleration and jerk (Sec. 2.4 step 7(c), Sec. 2.5)
 // ---------------------------------------------------------------------------
@@ -106,6 +183,88 @@ __device__ __forceinline__ double norm3(double a, double b, double c) {
 // The slices of a particle are summed afterwards by the kernel that consumes
 // the force (corrector, initial steps, or output), in an order that depends
 // only on (n_act, n).
+// i particles of one lane: predicted state, index, softening, accumulators.
+struct ILane {
+  double x[kIPerLane], y[kIPerLane], z[kIPerLane];
+  double vx[kIPerLane], vy[kIPerLane], vz[kIPerLane], e2[kIPerLane];
+  int g[kIPerLane], pos[kIPerLane];
+  Acc6 A[kIPerLane];
+};
+
+// Pairs of one LDS tile of cnt j (first index jt). Lane jsub of each group of
+// LJ lanes takes j = jsub, jsub + LJ, ...: a uniform trip count over whole
+// groups of LJ (scalar loop control, no per-lane exit masks), then at most
+// one partial group.
+template <bool kMaskSelf>
+__device__ __forceinline__ void tile_pairs(const double (*sj)[kTileJ], int cnt, int LJ, int jsub,
+                                           int jt, double eps2, ILane& I) {
+  const int full = cnt & ~(LJ - 1);
+  auto pairs_with = [&](int k) {
+    const double xj = sj[0][k], yj = sj[1][k], zj = sj[2][k];
+    const double vxj = sj[3][k], vyj = sj[4][k], vzj = sj[5][k];
+    const double mj = sj[6][k];
+#pragma unroll
+    for (int q = 0; q < kIPerLane; ++q) {
+      if (kMaskSelf) {
+        // eps = 0: the j = i term (r = 0) is excluded explicitly.
+        const bool self = (jt + k) == I.g[q];
+        pair_fp64(I.x[q], I.y[q], I.z[q], I.vx[q], I.vy[q], I.vz[q], self ? I.x[q] + 1.0 : xj, yj,
+                  zj, vxj, vyj, vzj, self ? 0.0 : mj, eps2, I.A[q]);
+      } else {
+        // eps > 0: the j = i term is exactly zero (r = w = 0, finite q).
+        pair_fp64(I.x[q], I.y[q], I.z[q], I.vx[q], I.vy[q], I.vz[q], xj, yj, zj, vxj, vyj, vzj, mj,
+                  I.e2[q], I.A[q]);
+      }
+    }
+  };
+#pragma unroll 2
+  for (int kk = 0; kk < full; kk += LJ) pairs_with(kk + jsub);
+  if (full + jsub < cnt) pairs_with(full + jsub);
+}
+
+// Butterfly over the LJ lanes that share an i (consecutive lanes), then the
+// central particle's pairs (softened with eps_bh, once per i, on slice 0;
+// bx.. its predicted state), then the slice partials by list position.
+template <bool kCentral>
+__device__ __forceinline__ void finish_item(const Dev& d, const Consts& c, int LJ, int jsub,
+                                            int slice, int n_act, ILane& I, double bx, double by,
+                                            double bz, double bvx, double bvy, double bvz) {
+  for (int off = LJ >> 1; off > 0; off >>= 1) {
+#pragma unroll
+    for (int q = 0; q < kIPerLane; ++q) {
+      I.A[q].ax += shfl_xor_d(I.A[q].ax, off);
+      I.A[q].ay += shfl_xor_d(I.A[q].ay, off);
+      I.A[q].az += shfl_xor_d(I.A[q].az, off);
+      I.A[q].jx += shfl_xor_d(I.A[q].jx, off);
+      I.A[q].jy += shfl_xor_d(I.A[q].jy, off);
+      I.A[q].jz += shfl_xor_d(I.A[q].jz, off);
+    }
+  }
+  if (kCentral && slice == 0 && jsub == 0) {
+    const int b = c.bh;
+    const double bm = d.m[b];
+#pragma unroll
+    for (int q = 0; q < kIPerLane; ++q)
+      if (I.g[q] != b)
+        pair_fp64(I.x[q], I.y[q], I.z[q], I.vx[q], I.vy[q], I.vz[q], bx, by, bz, bvx, bvy, bvz, bm,
+                  c.eps2_bh, I.A[q]);
+  }
+  if (jsub == 0) {
+#pragma unroll
+    for (int q = 0; q < kIPerLane; ++q) {
+      if (I.pos[q] < n_act) {
+        double* o = d.part + (size_t)slice * 6 * n_act + I.pos[q];
+        o[0 * (size_t)n_act] = I.A[q].ax;
+        o[1 * (size_t)n_act] = I.A[q].ay;
+        o[2 * (size_t)n_act] = I.A[q].az;
+        o[3 * (size_t)n_act] = I.A[q].jx;
+        o[4 * (size_t)n_act] = I.A[q].jy;
+        o[5 * (size_t)n_act] = I.A[q].jz;
+      }
+    }
+  }
+}
+
 template <bool kMaskSelf, bool kCentral>
 __device__ __forceinline__ void force_body(const Dev& d, const Consts& c, int blk, int nblk) {
   const Sched* __restrict__ sc = d.sc;
@@ -115,7 +274,6 @@ __device__ __forceinline__ void force_body(const Dev& d, const Consts& c, int bl
   const int n = c.n;
   const Plan p = sc->plan;
   if (blk >= p.items) return;
-  const double eps2 = c.eps2;
   const double* __restrict__ px = d.px;
   const double* __restrict__ py = d.py;
   const double* __restrict__ pz = d.pz;
@@ -123,9 +281,8 @@ __device__ __forceinline__ void force_body(const Dev& d, const Consts& c, int bl
   const double* __restrict__ pvy = d.pvy;
   const double* __restrict__ pvz = d.pvz;
   // With a central particle its mass is zero in the j stream (jm); its pairs
-  // are added separately below with their own softening.
+  // are added separately with their own softening.
   const double* __restrict__ pm = kCentral ? d.jm : d.m;
-  double* __restrict__ part = d.part;
 
   __shared__ double sj[7][kTileJ];
   const int tid = threadIdx.x;
@@ -140,27 +297,24 @@ __device__ __forceinline__ void force_body(const Dev& d, const Consts& c, int bl
     const int j0 = slice * p.len;
     const int j1 = min(n, j0 + p.len);
 
-    int pos[kIPerLane], gi[kIPerLane];
-    double xi[kIPerLane], yi[kIPerLane], zi[kIPerLane];
-    double vxi[kIPerLane], vyi[kIPerLane], vzi[kIPerLane], e2i[kIPerLane];
-    Acc6 A[kIPerLane];
+    ILane I;
 #pragma unroll
     for (int q = 0; q < kIPerLane; ++q) {
-      pos[q] = itile * p.it + ilane + q * ilanes;
+      I.pos[q] = itile * p.it + ilane + q * ilanes;
       // The predicted state of the active list is stored by list position
       // (one load level instead of an index gather).
-      const int k = min(pos[q], n_act - 1);
-      gi[q] = (kMaskSelf || kCentral) ? d.active[k] : 0;
+      const int k = min(I.pos[q], n_act - 1);
+      I.g[q] = (kMaskSelf || kCentral) ? d.active[k] : 0;
       // Softening enters only as the addend of r.r, so a per-i value costs
       // nothing: the central particle takes eps_bh for all of its pairs.
-      e2i[q] = (kCentral && gi[q] == c.bh) ? c.eps2_bh : eps2;
-      xi[q] = d.ix[k];
-      yi[q] = d.iy[k];
-      zi[q] = d.iz[k];
-      vxi[q] = d.ivx[k];
-      vyi[q] = d.ivy[k];
-      vzi[q] = d.ivz[k];
-      A[q] = Acc6{0, 0, 0, 0, 0, 0};
+      I.e2[q] = (kCentral && I.g[q] == c.bh) ? c.eps2_bh : c.eps2;
+      I.x[q] = d.ix[k];
+      I.y[q] = d.iy[k];
+      I.z[q] = d.iz[k];
+      I.vx[q] = d.ivx[k];
+      I.vy[q] = d.ivy[k];
+      I.vz[q] = d.ivz[k];
+      I.A[q] = Acc6{0, 0, 0, 0, 0, 0};
     }
 
     // Tile loads and LDS stores are lane-uniform (indices clamped into the
@@ -184,69 +338,15 @@ __device__ __forceinline__ void force_body(const Dev& d, const Consts& c, int bl
       sj[6][tid] = rm;
       __syncthreads();
       if (jt + kTileJ < j1) load_tile(jt + kTileJ);
-      // Uniform trip count over whole groups of LJ j (scalar loop control,
-      // no per-lane exit masks), then at most one partial group.
-      const int full = cnt & ~(LJ - 1);
-      auto pairs_with = [&](int k) {
-        const double xj = sj[0][k], yj = sj[1][k], zj = sj[2][k];
-        const double vxj = sj[3][k], vyj = sj[4][k], vzj = sj[5][k];
-        const double mj = sj[6][k];
-#pragma unroll
-        for (int q = 0; q < kIPerLane; ++q) {
-          if (kMaskSelf) {
-            // eps = 0: the j = i term (r = 0) is excluded explicitly.
-            const bool self = (jt + k) == gi[q];
-            pair_fp64(xi[q], yi[q], zi[q], vxi[q], vyi[q], vzi[q], self ? xi[q] + 1.0 : xj, yj,
-                      zj, vxj, vyj, vzj, self ? 0.0 : mj, eps2, A[q]);
-          } else {
-            // eps > 0: the j = i term is exactly zero (r = w = 0, finite q).
-            pair_fp64(xi[q], yi[q], zi[q], vxi[q], vyi[q], vzi[q], xj, yj, zj, vxj, vyj, vzj, mj,
-                      e2i[q], A[q]);
-          }
-        }
-      };
-#pragma unroll 2
-      for (int kk = 0; kk < full; kk += LJ) pairs_with(kk + jsub);
-      if (full + jsub < cnt) pairs_with(full + jsub);
+      tile_pairs<kMaskSelf>(sj, cnt, LJ, jsub, jt, c.eps2, I);
     }
-
-    // Butterfly over the LJ lanes that share an i (consecutive lanes).
-    for (int off = LJ >> 1; off > 0; off >>= 1) {
-#pragma unroll
-      for (int q = 0; q < kIPerLane; ++q) {
-        A[q].ax += shfl_xor_d(A[q].ax, off);
-        A[q].ay += shfl_xor_d(A[q].ay, off);
-        A[q].az += shfl_xor_d(A[q].az, off);
-        A[q].jx += shfl_xor_d(A[q].jx, off);
-        A[q].jy += shfl_xor_d(A[q].jy, off);
-        A[q].jz += shfl_xor_d(A[q].jz, off);
-      }
-    }
-    if (kCentral && slice == 0 && jsub == 0) {
-      // The central particle as j, softened with eps_bh, once per i.
+    double bx = 0, by = 0, bz = 0, bvx = 0, bvy = 0, bvz = 0;
+    if (kCentral) {
       const int b = c.bh;
-      const double bx = px[b], by = py[b], bz = pz[b];
-      const double bvx = pvx[b], bvy = pvy[b], bvz = pvz[b], bm = d.m[b];
-#pragma unroll
-      for (int q = 0; q < kIPerLane; ++q)
-        if (gi[q] != b)
-          pair_fp64(xi[q], yi[q], zi[q], vxi[q], vyi[q], vzi[q], bx, by, bz, bvx, bvy, bvz, bm,
-                    c.eps2_bh, A[q]);
+      bx = px[b]; by = py[b]; bz = pz[b];
+      bvx = pvx[b]; bvy = pvy[b]; bvz = pvz[b];
     }
-    if (jsub == 0) {
-#pragma unroll
-      for (int q = 0; q < kIPerLane; ++q) {
-        if (pos[q] < n_act) {
-          double* o = part + (size_t)slice * 6 * n_act + pos[q];
-          o[0 * (size_t)n_act] = A[q].ax;
-          o[1 * (size_t)n_act] = A[q].ay;
-          o[2 * (size_t)n_act] = A[q].az;
-          o[3 * (size_t)n_act] = A[q].jx;
-          o[4 * (size_t)n_act] = A[q].jy;
-          o[5 * (size_t)n_act] = A[q].jz;
-        }
-      }
-    }
+    finish_item<kCentral>(d, c, LJ, jsub, slice, n_act, I, bx, by, bz, bvx, bvy, bvz);
   }
 }
 
@@ -394,7 +494,7 @@ __device__ __forceinline__ void correct_body(const Dev& d, const Consts& c, int 
     d.ax[i] = f[0]; d.ay[i] = f[1]; d.az[i] = f[2];
     d.jx[i] = f[3]; d.jy[i] = f[4]; d.jz[i] = f[5];
     d.tick[i] = t_next;
-    d.lev[i] = nl;
+    d.lev[i] = (unsigned char)nl;
     if (nl != lv) {
       atomicAdd(&bk.hist[lv], -1);
       atomicAdd(&bk.hist[nl], 1);
@@ -441,7 +541,7 @@ __global__ __launch_bounds__(kBlock) void k_init_dt(Dev d, Consts c) {
     d.ax[i] = f[0]; d.ay[i] = f[1]; d.az[i] = f[2];
     d.jx[i] = f[3]; d.jy[i] = f[4]; d.jz[i] = f[5];
     d.tick[i] = t_now;
-    d.lev[i] = nl;
+    d.lev[i] = (unsigned char)nl;
     atomicAdd(&bk.hist[nl], 1);
   }
   __syncthreads();
@@ -513,7 +613,7 @@ __device__ __forceinline__ void predict_body(const Dev& d, const Consts& c, int 
   const double* __restrict__ jy = d.jy;
   const double* __restrict__ jz = d.jz;
   const long long* __restrict__ tick = d.tick;
-  const int* __restrict__ lev = d.lev;
+  const unsigned char* __restrict__ lev = d.lev;
   double* __restrict__ px = d.px;
   double* __restrict__ py = d.py;
   double* __restrict__ pz = d.pz;
@@ -534,8 +634,7 @@ __device__ __forceinline__ void predict_body(const Dev& d, const Consts& c, int 
   double* __restrict__ ijy = d.ijy;
   double* __restrict__ ijz = d.ijz;
   int* __restrict__ ilev = d.ilev;
-  __shared__ long long s_tnow, s_tend, s_tnext;
-  __shared__ int s_hist[kMaxLevels + 1];
+  __shared__ long long s_tnext;
   __shared__ int s_kthr, s_done, s_base;
   __shared__ int s_wcount[kBlock / 64];
   const int tid = threadIdx.x;
@@ -549,40 +648,40 @@ __device__ __forceinline__ void predict_body(const Dev& d, const Consts& c, int 
   const double j_x = jx[jj], j_y = jy[jj], j_z = jz[jj];
   const long long tj = tick[jj];
   const int lj = lev[jj];
-  if (tid <= kmax) s_hist[tid] = sc->hist[tid];
-  if (tid == 64) s_tnow = sc->t_now;
-  if (tid == 65) s_tend = sc->t_end;
-  __syncthreads();
-  if (tid == 0) {
+  // The step, by wave 0 (next_step_wave, make_plan_wave).
+  const int wave = tid >> 6, lane = tid & 63;
+  if (wave == 0) {
+    const int h = lane <= kmax ? sc->hist[lane] : 0;
+    const long long t_now = sc->t_now;
     long long t_next;
     int kthr, nact = 0, done = 0;
     if (mode == kPredAuto) {
-      int kmx = 0;
-      for (int k = kmax; k >= 0; --k)
-        if (s_hist[k] > 0) { kmx = k; break; }
-      const long long step = 1LL << (kmax - kmx);
-      t_next = (s_tnow / step + 1) * step;
-      const int tz = __builtin_ctzll((unsigned long long)t_next);
-      kthr = max(0, kmax - tz);
-      for (int k = kthr; k <= kmax; ++k) nact += s_hist[k];
-      done = t_next > s_tend;
+      const NextStep nx = next_step_wave(h, lane, kmax, t_now, sc->t_end, count_bits(n));
+      t_next = nx.t_next;
+      kthr = nx.kthr;
+      nact = nx.n_act;
+      done = nx.done;
     } else if (mode == kPredAll) {
-      t_next = s_tnow;
+      t_next = t_now;
       kthr = 0;
       nact = n;
     } else {
-      t_next = s_tnow;
+      t_next = t_now;
       kthr = kmax + 1;  // nobody active
     }
-    s_tnext = t_next;
-    s_kthr = kthr;
-    s_done = done;
-    if (blk == 0) {
-      sc->t_next = t_next;
-      sc->kthr = kthr;
-      sc->n_act = nact;
-      sc->done = done;
-      if (nact > 0) sc->plan = make_plan(nact, n);
+    Plan p{};
+    if (blk == 0 && nact > 0) p = make_plan_wave(nact, n, lane);
+    if (lane == 0) {
+      s_tnext = t_next;
+      s_kthr = kthr;
+      s_done = done;
+      if (blk == 0) {
+        sc->t_next = t_next;
+        sc->kthr = kthr;
+        sc->n_act = nact;
+        sc->done = done;
+        if (nact > 0) sc->plan = p;
+      }
     }
   }
   __syncthreads();
@@ -593,21 +692,13 @@ __device__ __forceinline__ void predict_body(const Dev& d, const Consts& c, int 
   if (j < n) {
     const double dt = (mode == kPredExplicit) ? t_explicit - (double)tj * dt_min
                                               : (double)(s_tnext - tj) * dt_min;
-    const double h2 = 0.5 * dt, h3 = dt * (1.0 / 3.0);
-    // x + dt (v + dt/2 (a + dt/3 jerk)),  v + dt (a + dt/2 jerk)
-    o[0] = fma(dt, fma(h2, fma(h3, j_x, a_x), v_x), x0);
-    o[1] = fma(dt, fma(h2, fma(h3, j_y, a_y), v_y), y0);
-    o[2] = fma(dt, fma(h2, fma(h3, j_z, a_z), v_z), z0);
-    o[3] = fma(dt, fma(h2, j_x, a_x), v_x);
-    o[4] = fma(dt, fma(h2, j_y, a_y), v_y);
-    o[5] = fma(dt, fma(h2, j_z, a_z), v_z);
+    taylor6(dt, x0, y0, z0, v_x, v_y, v_z, a_x, a_y, a_z, j_x, j_y, j_z, o);
     px[j] = o[0]; py[j] = o[1]; pz[j] = o[2];
     pvx[j] = o[3]; pvy[j] = o[4]; pvz[j] = o[5];
     act = lj >= s_kthr;
   }
   // Workgroup compaction of the active flags.
   const unsigned long long ball = __ballot(act);
-  const int wave = tid >> 6, lane = tid & 63;
   const int before = __popcll(ball & ((1ULL << lane) - 1ULL));
   if (lane == 0) s_wcount[wave] = __popcll(ball);
   __syncthreads();
@@ -759,7 +850,7 @@ __global__ void k_load(Sched* __restrict__ sc, int n, int bh, const double* __re
                        double* __restrict__ vz, double* __restrict__ ax, double* __restrict__ ay,
                        double* __restrict__ az, double* __restrict__ jx, double* __restrict__ jy,
                        double* __restrict__ jz, long long* __restrict__ tick,
-                       int* __restrict__ lev) {
+                       unsigned char* __restrict__ lev) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double mi = m_in[i];
@@ -844,7 +935,7 @@ __global__ void k_get_state(int n, int kmax, double dt_min, const double* __rest
                             const double* __restrict__ ay, const double* __restrict__ az,
                             const double* __restrict__ jx, const double* __restrict__ jy,
                             const double* __restrict__ jz, const long long* __restrict__ tick,
-                            const int* __restrict__ lev, double* __restrict__ xo,
+                            const unsigned char* __restrict__ lev, double* __restrict__ xo,
                             double* __restrict__ vo, double* __restrict__ ao,
                             double* __restrict__ jo, double* __restrict__ to,
                             double* __restrict__ dto) {
@@ -871,7 +962,7 @@ __global__ void k_set_state(Sched* __restrict__ sc, int n, int kmax, double dt_m
                             double* __restrict__ ay, double* __restrict__ az,
                             double* __restrict__ jx, double* __restrict__ jy,
                             double* __restrict__ jz, long long* __restrict__ tick,
-                            int* __restrict__ lev) {
+                            unsigned char* __restrict__ lev) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   bool ok = fin3(xi[3 * i], xi[3 * i + 1], xi[3 * i + 2]) &&
@@ -895,7 +986,7 @@ __global__ void k_set_state(Sched* __restrict__ sc, int n, int kmax, double dt_m
   ax[i] = ai[3 * i]; ay[i] = ai[3 * i + 1]; az[i] = ai[3 * i + 2];
   jx[i] = ji[3 * i]; jy[i] = ji[3 * i + 1]; jz[i] = ji[3 * i + 2];
   tick[i] = tk;
-  lev[i] = lv;
+  lev[i] = (unsigned char)lv;
   atomicAdd(&sc->hist[lv], 1);
 }
 
