@@ -141,6 +141,12 @@ def main():
     if args.workload == "serving":
         serving_bench(args)
         return
+    if args.workload == "plummer_imf_n262144":
+        mixed_bench(args)
+        return
+    if args.workload == "plummer_bh_n1048576":
+        central_bench(args)
+        return
 
     w = WORKLOADS[args.workload]
     n, t_end, dt_max = w["n"], w["t_end"], w["dt_max"]
@@ -232,6 +238,130 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     cl.close()
+    print(json.dumps(out), flush=True)
+
+
+def _rel_rows(a, b):
+    import torch
+    num = torch.linalg.vector_norm(a - b, dim=1)
+    den = torch.linalg.vector_norm(b, dim=1).clamp_min(1e-300)
+    return float((num / den).max())
+
+
+def mixed_bench(args):
+    """Full O(N^2) force and jerk of the mixed-precision workload (Plummer
+    N = 262144, power-law IMF, eps 1e-4) in FP64 and in mixed precision on
+    the same state: pair interactions per second of each, and the largest
+    per-particle relative difference of the mixed result from the FP64 one
+    (the tests bound both against the oracle)."""
+    import torch
+
+    from paper_1702_00440_amd import gravidy as g
+    from synth_inputs import WORKLOADS, plummer_imf
+
+    w = WORKLOADS["plummer_imf_n262144"]
+    n = w["n"]
+    dev = torch.device("cuda:0")
+    m, x, v = plummer_imf(n, w["seed"])
+    idx = torch.arange(n, dtype=torch.int32, device=dev)
+    res = {}
+    for mode, flags in (("fp64", 0), ("mixed", g.GD_FLAG_MIXED)):
+        cl = g.Cluster(m, x, v, eta=w["eta"], eps=w["eps"], dt_max=w["dt_max"], dt_min=w["dt_min"],
+                       device=dev, flags=flags)
+        acc = torch.empty(n, 3, dtype=torch.float64, device=dev)
+        jrk = torch.empty_like(acc)
+        times = []
+        for k in range(args.warmup + args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g.gd_predict(cl.ctx, 0.0)
+            g.gd_force(cl.ctx, idx, acc, jrk)
+            torch.cuda.synchronize()
+            if k >= args.warmup:
+                times.append(time.perf_counter() - t0)
+        cl.close()
+        t = sum(times) / len(times)
+        res[mode] = {"value": n * n / t, "ms_per_step": t * 1e3, "acc": acc, "jerk": jrk}
+    ra = _rel_rows(res["mixed"]["acc"], res["fp64"]["acc"])
+    rj = _rel_rows(res["mixed"]["jerk"], res["fp64"]["jerk"])
+    ach = {k: FLOPS_PER_PAIR * res[k]["value"] / 1e12 for k in res}
+    out = {
+        "metric": "pair-interactions/s (acc+jerk)",
+        "value": res["mixed"]["value"],
+        "unit": "pair-interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res["mixed"]["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 pair arithmetic, f64 differences/state/accumulators",
+        "data": "synthetic",
+        "config": {"workload": "plummer_imf_n262144_full_force", "n": n, "eps": w["eps"], "seed": w["seed"],
+                   "ic": "Plummer sphere, power-law IMF slope -2.35 on [0.1, 100], total mass 1",
+                   "step": "one O(N^2) evaluation of all N (gd_predict + gd_force)"},
+        "fp64": {"value": res["fp64"]["value"], "ms_per_step": res["fp64"]["ms_per_step"],
+                 "achieved_tflops": ach["fp64"]},
+        "mixed_vs_fp64_max_rel_diff": {"acc": ra, "jerk": rj},
+        "roofline": {"bound": "alu", "achieved": ach["mixed"], "peak": PEAK_FP64_VECTOR_TFLOPS,
+                     "unit": "TFLOP/s", "frac": ach["mixed"] / PEAK_FP64_VECTOR_TFLOPS, "traffic": None,
+                     "note": "unpacked FP32 issues at the FP64 rate on this build (packed FP32 disabled)"},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def central_bench(args):
+    """Plummer sphere of 2^20 stars plus a central particle (mass 0.01, at rest
+    at the origin; eps 1e-4 between stars, 1e-6 with the central particle),
+    mixed precision, block steps down to dt_min = 2^-22, integrated to
+    t = 1/8 in chunks of dt_max = 1/64 (one progress line each): pair
+    interactions per second over the whole integration."""
+    import torch
+
+    from paper_1702_00440_amd import gravidy as g
+    from synth_inputs import WORKLOADS, plummer_with_bh
+
+    w = WORKLOADS["plummer_bh_n1048576"]
+    dev = torch.device("cuda:0")
+    m, x, v = plummer_with_bh(w["n_stars"], w["seed"], m_bh=w["m_bh"])
+    n = m.shape[0]
+    md, xd, vd = (torch.as_tensor(a).to(dev).contiguous() for a in (m, x, v))
+    cl = g.Cluster(m, x, v, eta=w["eta"], eps=w["eps"], dt_max=w["dt_max"], dt_min=w["dt_min"], device=dev,
+                   eps_bh=w["eps_bh"], bh_index=w["n_stars"], flags=g.GD_FLAG_MIXED)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.gd_reinit(cl.ctx, md, xd, vd)
+    n_chunks = int(round(w["t_end"] / w["dt_max"]))
+    for k in range(1, n_chunks + 1):
+        st = g.gd_step_to(cl.ctx, k * w["dt_max"])
+        print(f"# t={st['t']:.6g} block_steps={st['block_steps']} elapsed={time.perf_counter() - t0:.1f}s",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    cl.close()
+    pairs = st["pair_interactions"] + n * n
+    out = {
+        "metric": "pair-interactions/s (acc+jerk)",
+        "value": pairs / el,
+        "unit": "pair-interactions/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 0,
+        "ms_per_step": el * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 pair arithmetic, f64 differences/state/accumulators; central pairs f64",
+        "data": "synthetic",
+        "config": {"workload": "plummer_bh_n1048577_mixed_t0.125", "n": n, "eps": w["eps"],
+                   "eps_bh": w["eps_bh"], "m_bh": w["m_bh"], "dt_min": w["dt_min"], "dt_max": w["dt_max"],
+                   "t_end": w["t_end"]},
+        "energy_drift": abs(st["e"] - st["e0"]) / abs(st["e0"]),
+        "block_steps": st["block_steps"],
+        "particle_steps": st["particle_steps"],
+        "dtmin_clamps": st["dtmin_clamps"],
+    }
     print(json.dumps(out), flush=True)
 
 

@@ -132,7 +132,7 @@ const char* check_params(const gd_params* p, int64_t n, int* kmax_out) {
     return "dt_max and dt_min must be powers of two with dt_min <= dt_max";
   const int kmax = (int)std::lround(std::log2(p->dt_max / p->dt_min));
   if (kmax > 40) return "log2(dt_max / dt_min) must be <= 40";
-  if (p->flags != 0) return "flags must be 0";
+  if ((p->flags & ~GD_FLAG_MIXED) != 0) return "flags: unknown bits";
   *kmax_out = kmax;
   return nullptr;
 }
@@ -148,6 +148,7 @@ Consts make_consts(const gd_params* p, int64_t n, int kmax) {
   c.bh = (int)p->bh_index;
   c.eps2_bh = p->bh_index >= 0 ? p->eps_bh * p->eps_bh : c.eps2;
   launch_grids((int)n, &c.force_grid, &c.correct_grid);
+  c.mixed = (p->flags & GD_FLAG_MIXED) ? 1 : 0;
   return c;
 }
 
@@ -710,7 +711,7 @@ gd_status pool_build_graph(gd_pool* P) {
                 "begin capture"));
   hipError_t e = hipSuccess;
   for (int k = 0; k < kPoolSteps && e == hipSuccess; ++k)
-    e = launch_pool_step(P->d_slots, P->d_tab, P->capture_stream);
+    e = launch_pool_step(P->d_slots, P->d_tab, (P->p.flags & GD_FLAG_MIXED) != 0, P->capture_stream);
   if (e == hipSuccess) e = launch_pool_status(P->d_slots, P->d_tab, P->d_status, P->capture_stream);
   hipError_t e2 = hipStreamEndCapture(P->capture_stream, &g);
   if (e != hipSuccess || e2 != hipSuccess) {

@@ -157,6 +157,7 @@ struct Consts {
   int force_grid;    // workgroups of a force launch
   int correct_grid;  // workgroups of a corrector launch
   int bh;            // index of the central particle, -1 if none
+  int mixed;         // 1: pair arithmetic in mixed precision (GD_FLAG_MIXED)
   double dt_min, dt_max, eta, eps2, eps2_bh;
 };
 
@@ -213,7 +214,7 @@ struct PoolStatus {
   int done, nonfinite;
 };
 
-hipError_t launch_pool_step(const PoolSlot* slots, const PoolTable* tab, hipStream_t s);
+hipError_t launch_pool_step(const PoolSlot* slots, const PoolTable* tab, bool mixed, hipStream_t s);
 // Lagrange radii of the ascending fractions frac[0..n_frac) into out[0..n_frac),
 // Eq. (5) into out[n_frac], the half-mass radius into out[n_frac + 1].
 hipError_t launch_diagnostics(const Dev& d, const Consts& c, const double* frac, int n_frac,

@@ -64,6 +64,43 @@ __device__ __forceinline__ void pair_fp64(double xi, double yi, double zi, doubl
   A.jz = fma(mq3, wz, A.jz);
 }
 
+// FP32 accumulators of one i particle over one LDS tile (mixed precision).
+struct Acc6f {
+  float ax, ay, az, jx, jy, jz;
+};
+
+// The same pair in mixed precision. The scalar factors are FP64: the
+// differences r = x_j - x_i and w = v_j - v_i, s = r.r + eps^2, r.w, and
+// q = s^(-1/2) from v_rsq_f64 with one Newton step y (3 - s y^2) / 2 (about
+// 2^-47, ample for the FP32 results); m q^3 and -3 (r.w) q^2 are then rounded
+// to FP32 once each. The vector terms m q^3 r and m q^3 (w - 3 (r.w) q^2 r)
+// are formed and summed in FP32 from r and w rounded to FP32; the caller
+// folds the FP32 sums of each tile into FP64 accumulators. (Rounding q
+// itself to FP32 before forming q^2 and q^3 would dominate the jerk error.)
+__device__ __forceinline__ void pair_mixed(double xi, double yi, double zi, double vxi, double vyi,
+                                           double vzi, double xj, double yj, double zj, double vxj,
+                                           double vyj, double vzj, double mj, double eps2,
+                                           Acc6f& A) {
+  const double dx = xj - xi, dy = yj - yi, dz = zj - zi;
+  const double dvx = vxj - vxi, dvy = vyj - vyi, dvz = vzj - vzi;
+  const double s = fma(dz, dz, fma(dy, dy, fma(dx, dx, eps2)));
+  const double rv = fma(dz, dvz, fma(dy, dvy, dx * dvx));
+  const double y = __builtin_amdgcn_rsq(s);
+  const double q = fma(y * fma(-s, y * y, 1.0), 0.5, y);
+  const double q2 = q * q;
+  const float mq3 = (float)((mj * q) * q2);
+  const float b3 = (float)((rv * q2) * -3.0);
+  const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
+  const float fvx = (float)dvx, fvy = (float)dvy, fvz = (float)dvz;
+  A.ax = fmaf(mq3, fx, A.ax);
+  A.ay = fmaf(mq3, fy, A.ay);
+  A.az = fmaf(mq3, fz, A.az);
+  const float wx = fmaf(b3, fx, fvx), wy = fmaf(b3, fy, fvy), wz = fmaf(b3, fz, fvz);
+  A.jx = fmaf(mq3, wx, A.jx);
+  A.jy = fmaf(mq3, wy, A.jy);
+  A.jz = fmaf(mq3, wz, A.jz);
+}
+
 __device__ __forceinline__ double shfl_xor_d(double v, int mask) { return __shfl_xor(v, mask, 64); }
 
 // ---------------------------------------------------------------------------
@@ -189,37 +226,55 @@ struct ILane {
   double vx[kIPerLane], vy[kIPerLane], vz[kIPerLane], e2[kIPerLane];
   int g[kIPerLane], pos[kIPerLane];
   Acc6 A[kIPerLane];
+  Acc6f Af[kIPerLane];  // mixed precision: sums of the current tile
 };
 
 // Pairs of one LDS tile of cnt j (first index jt). Lane jsub of each group of
 // LJ lanes takes j = jsub, jsub + LJ, ...: a uniform trip count over whole
 // groups of LJ (scalar loop control, no per-lane exit masks), then at most
 // one partial group.
-template <bool kMaskSelf>
+template <bool kMaskSelf, bool kMixed>
 __device__ __forceinline__ void tile_pairs(const double (*sj)[kTileJ], int cnt, int LJ, int jsub,
                                            int jt, double eps2, ILane& I) {
   const int full = cnt & ~(LJ - 1);
+  if (kMixed) {
+#pragma unroll
+    for (int q = 0; q < kIPerLane; ++q) I.Af[q] = Acc6f{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  }
   auto pairs_with = [&](int k) {
     const double xj = sj[0][k], yj = sj[1][k], zj = sj[2][k];
     const double vxj = sj[3][k], vyj = sj[4][k], vzj = sj[5][k];
     const double mj = sj[6][k];
 #pragma unroll
     for (int q = 0; q < kIPerLane; ++q) {
-      if (kMaskSelf) {
-        // eps = 0: the j = i term (r = 0) is excluded explicitly.
-        const bool self = (jt + k) == I.g[q];
-        pair_fp64(I.x[q], I.y[q], I.z[q], I.vx[q], I.vy[q], I.vz[q], self ? I.x[q] + 1.0 : xj, yj,
-                  zj, vxj, vyj, vzj, self ? 0.0 : mj, eps2, I.A[q]);
+      // eps = 0: the j = i term (r = 0) is excluded explicitly; with eps > 0
+      // it is exactly zero (r = w = 0, finite q).
+      const bool self = kMaskSelf && (jt + k) == I.g[q];
+      const double xjq = self ? I.x[q] + 1.0 : xj;
+      if (kMixed) {
+        pair_mixed(I.x[q], I.y[q], I.z[q], I.vx[q], I.vy[q], I.vz[q], xjq, yj, zj, vxj, vyj, vzj,
+                   self ? 0.0 : mj, kMaskSelf ? eps2 : I.e2[q], I.Af[q]);
       } else {
-        // eps > 0: the j = i term is exactly zero (r = w = 0, finite q).
-        pair_fp64(I.x[q], I.y[q], I.z[q], I.vx[q], I.vy[q], I.vz[q], xj, yj, zj, vxj, vyj, vzj, mj,
-                  I.e2[q], I.A[q]);
+        pair_fp64(I.x[q], I.y[q], I.z[q], I.vx[q], I.vy[q], I.vz[q], xjq, yj, zj, vxj, vyj, vzj,
+                  self ? 0.0 : mj, kMaskSelf ? eps2 : I.e2[q], I.A[q]);
       }
     }
   };
 #pragma unroll 2
   for (int kk = 0; kk < full; kk += LJ) pairs_with(kk + jsub);
   if (full + jsub < cnt) pairs_with(full + jsub);
+  if (kMixed) {
+    // At most kTileJ / LJ terms per lane in FP32, then into FP64.
+#pragma unroll
+    for (int q = 0; q < kIPerLane; ++q) {
+      I.A[q].ax += (double)I.Af[q].ax;
+      I.A[q].ay += (double)I.Af[q].ay;
+      I.A[q].az += (double)I.Af[q].az;
+      I.A[q].jx += (double)I.Af[q].jx;
+      I.A[q].jy += (double)I.Af[q].jy;
+      I.A[q].jz += (double)I.Af[q].jz;
+    }
+  }
 }
 
 // Butterfly over the LJ lanes that share an i (consecutive lanes), then the
@@ -265,7 +320,7 @@ __device__ __forceinline__ void finish_item(const Dev& d, const Consts& c, int L
   }
 }
 
-template <bool kMaskSelf, bool kCentral>
+template <bool kMaskSelf, bool kCentral, bool kMixed>
 __device__ __forceinline__ void force_body(const Dev& d, const Consts& c, int blk, int nblk) {
   const Sched* __restrict__ sc = d.sc;
   if (sc->done) return;
@@ -338,7 +393,7 @@ __device__ __forceinline__ void force_body(const Dev& d, const Consts& c, int bl
       sj[6][tid] = rm;
       __syncthreads();
       if (jt + kTileJ < j1) load_tile(jt + kTileJ);
-      tile_pairs<kMaskSelf>(sj, cnt, LJ, jsub, jt, c.eps2, I);
+      tile_pairs<kMaskSelf, kMixed>(sj, cnt, LJ, jsub, jt, c.eps2, I);
     }
     double bx = 0, by = 0, bz = 0, bvx = 0, bvy = 0, bvz = 0;
     if (kCentral) {
@@ -350,9 +405,9 @@ __device__ __forceinline__ void force_body(const Dev& d, const Consts& c, int bl
   }
 }
 
-template <bool kMaskSelf, bool kCentral>
+template <bool kMaskSelf, bool kCentral, bool kMixed>
 __global__ __launch_bounds__(kBlock) void k_force(Dev d, Consts c) {
-  force_body<kMaskSelf, kCentral>(d, c, blockIdx.x, gridDim.x);
+  force_body<kMaskSelf, kCentral, kMixed>(d, c, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1025,6 +1080,7 @@ __global__ __launch_bounds__(kBlock) void k_pool_predict(const PoolSlot* __restr
   }
 }
 
+template <bool kMixed>
 __global__ __launch_bounds__(kBlock) void k_pool_force(const PoolSlot* __restrict__ slots,
                                                        const PoolTable* __restrict__ tab) {
   __shared__ int s_off[kMaxPool + 1], s_order[kMaxPool], s_n[kMaxPool];
@@ -1050,7 +1106,7 @@ __global__ __launch_bounds__(kBlock) void k_pool_force(const PoolSlot* __restric
   for (int g = blockIdx.x; g < total; g += gridDim.x) {
     const int k = pool_find(s_off, count, g);
     const PoolSlot& ps = slots[s_order[k]];
-    force_body<false, false>(ps.d, ps.c, g - s_off[k], s_n[k]);
+    force_body<false, false, kMixed>(ps.d, ps.c, g - s_off[k], s_n[k]);
   }
 }
 
@@ -1247,7 +1303,10 @@ hipError_t launch_predict(const Dev& d, const Consts& c, int mode, double t_expl
 
 hipError_t launch_force(const Dev& d, const Consts& c, hipStream_t s, hipEvent_t ev_start,
                         hipEvent_t ev_stop) {
-  auto kern = c.bh >= 0 ? k_force<false, true> : (c.eps2 > 0.0 ? k_force<false, false> : k_force<true, false>);
+  auto kern = c.mixed ? (c.bh >= 0 ? k_force<false, true, true>
+                                    : (c.eps2 > 0.0 ? k_force<false, false, true> : k_force<true, false, true>))
+                      : (c.bh >= 0 ? k_force<false, true, false>
+                                   : (c.eps2 > 0.0 ? k_force<false, false, false> : k_force<true, false, false>));
   if (ev_start) {
     // The events take the dispatch's own start and end timestamps.
     hipExtLaunchKernelGGL(kern, dim3(c.force_grid), dim3(kBlock), 0, s, ev_start, ev_stop, 0, d, c);
@@ -1353,11 +1412,14 @@ hipError_t launch_diagnostics(const Dev& d, const Consts& c, const double* frac,
   return hipGetLastError();
 }
 
-hipError_t launch_pool_step(const PoolSlot* slots, const PoolTable* tab, hipStream_t s) {
+hipError_t launch_pool_step(const PoolSlot* slots, const PoolTable* tab, bool mixed, hipStream_t s) {
   hipLaunchKernelGGL(k_pool_predict, dim3(kPoolGrid), dim3(kBlock), 0, s, slots, tab);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_pool_force, dim3(kPoolGrid), dim3(kBlock), 0, s, slots, tab);
+  if (mixed)
+    hipLaunchKernelGGL(k_pool_force<true>, dim3(kPoolGrid), dim3(kBlock), 0, s, slots, tab);
+  else
+    hipLaunchKernelGGL(k_pool_force<false>, dim3(kPoolGrid), dim3(kBlock), 0, s, slots, tab);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_pool_correct, dim3(kPoolGrid), dim3(kBlock), 0, s, slots, tab);

@@ -19,6 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgravidy_hip.so")
 
 GD_OK, GD_EINVAL, GD_ENOMEM, GD_EHIP, GD_ESTATE, GD_ENONFINITE = 0, -1, -2, -3, -4, -5
+GD_FLAG_MIXED = 1
 _NAMES = {GD_EINVAL: "GD_EINVAL", GD_ENOMEM: "GD_ENOMEM", GD_EHIP: "GD_EHIP",
           GD_ESTATE: "GD_ESTATE", GD_ENONFINITE: "GD_ENONFINITE"}
 
@@ -311,8 +312,9 @@ class Cluster:
     """One context plus the device workspace it owns (a torch uint8 tensor)."""
 
     def __init__(self, m, x, v, eta=0.01, eps=1e-4, dt_max=0.125, dt_min=2.0 ** -22,
-                 device="cuda", stream=None, eps_bh=None, bh_index=-1):
-        self.params = make_params(eta, eps, dt_max, dt_min, eps_bh=eps_bh, bh_index=bh_index)
+                 device="cuda", stream=None, eps_bh=None, bh_index=-1, flags=0):
+        self.params = make_params(eta, eps, dt_max, dt_min, flags=flags, eps_bh=eps_bh,
+                                  bh_index=bh_index)
         dev = torch.device(device)
         self.m = torch.as_tensor(m, dtype=torch.float64).to(dev).contiguous()
         self.n = self.m.shape[0]

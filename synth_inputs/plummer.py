@@ -147,4 +147,11 @@ def kepler_pair(m1: float = 0.5, m2: float = 0.5, a: float = 1.0, e: float = 0.0
 WORKLOADS = {
     "plummer_n1024": dict(n=1024, seed=1, eps=1e-4, eta=0.01, dt_max=0.125, dt_min=2.0 ** -22, t_end=1.0),
     "plummer_n16384": dict(n=16384, seed=1, eps=1e-4, eta=0.01, dt_max=0.125, dt_min=2.0 ** -22, t_end=1.0),
+    # power-law IMF (slope -2.35 on [0.1, 100], total mass 1): the mixed-precision workload
+    "plummer_imf_n262144": dict(n=262144, seed=5, eps=1e-4, eta=0.01, dt_max=0.125, dt_min=2.0 ** -22,
+                                t_end=0.125, imf=True),
+    # 2^20 equal-mass stars plus a central particle of mass 0.01 at rest at the origin
+    # (dt_max 1/64: the integration to 1/8 runs as 8 synchronised chunks)
+    "plummer_bh_n1048576": dict(n=1048576 + 1, n_stars=1048576, seed=7, eps=1e-4, eps_bh=1e-6, m_bh=0.01,
+                                eta=0.01, dt_max=1.0 / 64, dt_min=2.0 ** -22, t_end=0.125),
 }

@@ -63,7 +63,7 @@ def test_workspace_bytes_host_only():
     (dict(dt_max=0.1), "power"),
     (dict(dt_min=0.25), "power"),
     (dict(dt_min=2.0 ** -60), "40"),
-    (dict(flags=1), "flags"),
+    (dict(flags=2), "flags"),
 ])
 def test_init_rejects_bad_params_before_any_device_work(kw, msg):
     """Parameter validation happens on the host before any HIP call, so it can
