@@ -107,10 +107,13 @@ def main():
                     help="print the hash of the kernel sources that a counter summary is tied to")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES of device memory once (calibrates HBM byte counters)")
-    ap.add_argument("--requests", type=int, default=128, help="serving: number of clusters")
+    ap.add_argument("--requests", type=int, default=512, help="serving: number of clusters")
     ap.add_argument("--rho", type=float, default=1.0,
                     help="serving: arrival rate as a multiple of the sequential solve rate")
     ap.add_argument("--max-clusters", type=int, default=64, help="serving: pool slots")
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default=None,
+                    help="serving and central-particle workloads: pair arithmetic (default: fp64 for "
+                         "serving, mixed for the central-particle workload)")
     args = ap.parse_args()
     if args.kernel_hash:
         print(kernel_sources_sha256())
@@ -327,8 +330,9 @@ def central_bench(args):
     m, x, v = plummer_with_bh(w["n_stars"], w["seed"], m_bh=w["m_bh"])
     n = m.shape[0]
     md, xd, vd = (torch.as_tensor(a).to(dev).contiguous() for a in (m, x, v))
+    mixed = args.precision != "fp64"
     cl = g.Cluster(m, x, v, eta=w["eta"], eps=w["eps"], dt_max=w["dt_max"], dt_min=w["dt_min"], device=dev,
-                   eps_bh=w["eps_bh"], bh_index=w["n_stars"], flags=g.GD_FLAG_MIXED)
+                   eps_bh=w["eps_bh"], bh_index=w["n_stars"], flags=g.GD_FLAG_MIXED if mixed else 0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     g.gd_reinit(cl.ctx, md, xd, vd)
@@ -352,9 +356,10 @@ def central_bench(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 pair arithmetic, f64 differences/state/accumulators; central pairs f64",
+        "dtype": ("f32 pair arithmetic, f64 differences/state/accumulators; central pairs f64" if mixed
+                  else "f64"),
         "data": "synthetic",
-        "config": {"workload": "plummer_bh_n1048577_mixed_t0.125", "n": n, "eps": w["eps"],
+        "config": {"workload": f"plummer_bh_n1048577_{'mixed' if mixed else 'fp64'}_t0.125", "n": n, "eps": w["eps"],
                    "eps_bh": w["eps_bh"], "m_bh": w["m_bh"], "dt_min": w["dt_min"], "dt_max": w["dt_max"],
                    "t_end": w["t_end"]},
         "energy_drift": abs(st["e"] - st["e0"]) / abs(st["e0"]),
@@ -387,7 +392,9 @@ def serving_bench(args):
         m, x, v = plummer(n, 1000 + k)
         reqs.append(serving.Request(k, 0.0, torch.as_tensor(m).to(dev), torch.as_tensor(x).to(dev).contiguous(),
                                     torch.as_tensor(v).to(dev).contiguous(), t_end))
-    p = g.make_params(eta=0.01, eps=1e-4, dt_max=0.125, dt_min=2.0 ** -22)
+    mixed = args.precision == "mixed"
+    p = g.make_params(eta=0.01, eps=1e-4, dt_max=0.125, dt_min=2.0 ** -22,
+                      flags=g.GD_FLAG_MIXED if mixed else 0)
     # warm-up: one small solve each way
     serving.serve_sequential(p, reqs[:1])
     # sequential baseline, all requests available at once
@@ -426,9 +433,9 @@ def serving_bench(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32 pair arithmetic, f64 state" if mixed else "f64",
         "data": "synthetic",
-        "config": {"workload": "serving_plummer_n256-8192_t0.5", "requests": len(reqs), "rho": args.rho,
+        "config": {"workload": f"serving_plummer_n256-8192_t0.5_{'mixed' if mixed else 'fp64'}", "requests": len(reqs), "rho": args.rho,
                    "arrival_rate_per_s": lam, "max_clusters": args.max_clusters, "eps": 1e-4, "eta": 0.01},
         "value_kind": "capacity: all requests queued at t=0",
         "latency_p50_s": float(np.percentile(lat, 50)),

@@ -64,8 +64,9 @@ typedef struct {
   int32_t flags;     /* 0 or GD_FLAG_MIXED; other bits must be 0 */
 } gd_params;
 
-/* gd_params.flags: mixed-precision pair arithmetic in every force evaluation
- * of the context or pool (initial force, block steps, gd_force). Per pair,
+/* gd_params.flags: mixed-precision pair arithmetic (the alternative to FP64
+ * that Sec. 2.3 names) in every force evaluation of the context or pool
+ * (initial force, block steps, gd_force). Per pair,
  * the scalar factors (differences, r.r + eps^2, r.w, the inverse square
  * root, m q^3 and 3 (r.w) q^2) are FP64; the vector terms of Eq. (3) and of
  * its time derivative are formed in FP32 from the differences rounded to
