@@ -285,3 +285,22 @@ def test_diagnostics_against_oracle(n):
     with pytest.raises(g.GdError):
         g.gd_diagnostics(cl.ctx, [1.5])
     cl.close()
+
+
+@pytest.mark.parametrize("dtmin_exp", [8, 10])
+def test_dt_min_clamps_against_oracle(dtmin_exp):
+    """A coarse dt_min (2^-8, 2^-10) makes many steps clamp: the number of
+    clamps, block and particle steps match the oracle exactly, and the state
+    agrees to rounding."""
+    n = 512
+    m, x, v = plummer(n, 3)
+    dt_min = 2.0 ** -dtmin_exp
+    cl = g.Cluster(m, x, v, eta=ETA, eps=EPS, dt_max=DTMAX, dt_min=dt_min, device=DEV)
+    st = g.gd_step_to(cl.ctx, 0.125)
+    ref = oracle.State(m, x, v, EPS, ETA, DTMAX, dt_min, threads=8)
+    ref.run(0.125)
+    assert st["dtmin_clamps"] == ref.stats[3] > 0
+    assert st["block_steps"] == ref.stats[0]
+    assert st["particle_steps"] == ref.stats[1]
+    assert np.abs(host(cl.state()[0]) - ref.x).max() < 1e-10
+    cl.close()
