@@ -1081,8 +1081,8 @@ __global__ __launch_bounds__(kBlock) void k_pool_predict(const PoolSlot* __restr
 }
 
 template <bool kMixed>
-__global__ __launch_bounds__(kBlock) void k_pool_force(const PoolSlot* __restrict__ slots,
-                                                       const PoolTable* __restrict__ tab) {
+__device__ __forceinline__ void pool_force_body(const PoolSlot* __restrict__ slots,
+                                                const PoolTable* __restrict__ tab) {
   __shared__ int s_off[kMaxPool + 1], s_order[kMaxPool], s_n[kMaxPool];
   const int tid = threadIdx.x;
   const int count = tab->count;
@@ -1108,6 +1108,19 @@ __global__ __launch_bounds__(kBlock) void k_pool_force(const PoolSlot* __restric
     const PoolSlot& ps = slots[s_order[k]];
     force_body<false, false, kMixed>(ps.d, ps.c, g - s_off[k], s_n[k]);
   }
+}
+
+// The FP64 variant fits 128 VGPRs (4 waves per SIMD) with its few spills
+// outside the loops; the mixed one would spill inside the tile loop there and
+// runs at 3 waves per SIMD instead.
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_pool_force(
+    const PoolSlot* __restrict__ slots, const PoolTable* __restrict__ tab) {
+  pool_force_body<false>(slots, tab);
+}
+
+__global__ __launch_bounds__(kBlock) void k_pool_force_mixed(const PoolSlot* __restrict__ slots,
+                                                             const PoolTable* __restrict__ tab) {
+  pool_force_body<true>(slots, tab);
 }
 
 __global__ __launch_bounds__(kBlock) void k_pool_correct(const PoolSlot* __restrict__ slots,
@@ -1417,9 +1430,9 @@ hipError_t launch_pool_step(const PoolSlot* slots, const PoolTable* tab, bool mi
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (mixed)
-    hipLaunchKernelGGL(k_pool_force<true>, dim3(kPoolGrid), dim3(kBlock), 0, s, slots, tab);
+    hipLaunchKernelGGL(k_pool_force_mixed, dim3(kPoolGrid), dim3(kBlock), 0, s, slots, tab);
   else
-    hipLaunchKernelGGL(k_pool_force<false>, dim3(kPoolGrid), dim3(kBlock), 0, s, slots, tab);
+    hipLaunchKernelGGL(k_pool_force, dim3(kPoolGrid), dim3(kBlock), 0, s, slots, tab);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_pool_correct, dim3(kPoolGrid), dim3(kBlock), 0, s, slots, tab);
