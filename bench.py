@@ -119,7 +119,7 @@ def main():
         print(kernel_sources_sha256())
         return
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1 "
+        print("bench.py: the benchmark runs on one GPU only; --gpus must be 1 "
               "(the multi-GPU split is described, not built).", file=sys.stderr)
         sys.exit(2)
 
@@ -309,7 +309,7 @@ def mixed_bench(args):
         "mixed_vs_fp64_max_rel_diff": {"acc": ra, "jerk": rj},
         "roofline": {"bound": "alu", "achieved": ach["mixed"], "peak": PEAK_FP64_VECTOR_TFLOPS,
                      "unit": "TFLOP/s", "frac": ach["mixed"] / PEAK_FP64_VECTOR_TFLOPS, "traffic": None,
-                     "note": "unpacked FP32 issues at the FP64 rate on this build (packed FP32 disabled)"},
+                     "note": "unpacked FP32 issues at the FP64 rate (packed FP32 is disabled at compile time)"},
     }
     print(json.dumps(out), flush=True)
 
