@@ -103,7 +103,8 @@ gd_status gd_workspace_bytes(int64_t n, const gd_params* p, size_t* bytes);
  * by gd_stats as e0). Synchronises the stream.
  * Errors: GD_EINVAL for n < 2, a NULL pointer, eta <= 0, eps outside
  * {0} U [1e-30, inf), dt_max/dt_min not powers of two or dt_min > dt_max,
- * log2(dt_max/dt_min) > 40, or non-finite m/x/v or m < 0 (checked on the
+ * log2(dt_max/dt_min) > 40, flags other than 0 or GD_FLAG_MIXED, a bad
+ * central-particle setting, or non-finite m/x/v or m < 0 (checked on the
  * device); GD_ENOMEM if ws_bytes is too small; GD_EHIP on HIP failure. On
  * error *ctx is NULL.
  */
