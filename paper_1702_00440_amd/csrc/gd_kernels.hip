@@ -101,7 +101,60 @@ __device__ __forceinline__ void pair_mixed(double xi, double yi, double zi, doub
   A.jz = fmaf(mq3, wz, A.jz);
 }
 
-__device__ __forceinline__ double shfl_xor_d(double v, int mask) { return __shfl_xor(v, mask, 64); }
+// Value held by lane (lane ^ kOff) of the wave, kOff in {1, 2, 4, 8, 16, 32},
+// by register-only lane exchanges instead of the LDS crossbar: DPP quad
+// permutations (1, 2), a half-row mirror followed by a quad reversal (4), a
+// row rotation by 8 (8), and the permlane16/32 swaps (16, 32), of which each
+// lane takes the half that holds its partner. Every lane of the wave must be
+// active. The partner is exactly lane ^ kOff, so a butterfly built on it sums
+// in the same order as one built on __shfl_xor.
+template <int kOff>
+__device__ __forceinline__ int xor_partner_i(int v) {
+  if constexpr (kOff == 1) {
+    return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+  } else if constexpr (kOff == 2) {
+    return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+  } else if constexpr (kOff == 4) {
+    const int m = __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+    return __builtin_amdgcn_mov_dpp(m, 0x1B, 0xF, 0xF, false);         // quad_perm [3,2,1,0]
+  } else if constexpr (kOff == 8) {
+    return __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, false);  // row_ror:8
+  } else if constexpr (kOff == 16) {
+    const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    return (threadIdx.x & 16) ? r[0] : r[1];
+  } else {
+    static_assert(kOff == 32, "lane exchange offsets are 1..32");
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return (threadIdx.x & 32) ? r[0] : r[1];
+  }
+}
+
+template <int kOff>
+__device__ __forceinline__ double xor_partner_d(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)xor_partner_i<kOff>((int)(unsigned)b);
+  const unsigned hi = (unsigned)xor_partner_i<kOff>((int)(unsigned)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+template <int kOff, int kN>
+__device__ __forceinline__ void xor_add(double (&v)[kN]) {
+#pragma unroll
+  for (int k = 0; k < kN; ++k) v[k] += xor_partner_d<kOff>(v[k]);
+}
+
+// Sum of v over each aligned group of g consecutive lanes (g a power of two,
+// at most 64), left in every lane of the group: a butterfly with offsets
+// g/2, ..., 1 (one uniform branch per level).
+template <int kN>
+__device__ __forceinline__ void group_sum(double (&v)[kN], int g) {
+  if (g > 32) xor_add<32>(v);
+  if (g > 16) xor_add<16>(v);
+  if (g > 8) xor_add<8>(v);
+  if (g > 4) xor_add<4>(v);
+  if (g > 2) xor_add<2>(v);
+  if (g > 1) xor_add<1>(v);
+}
 
 // ---------------------------------------------------------------------------
 // Block time steps
@@ -284,15 +337,18 @@ template <bool kCentral>
 __device__ __forceinline__ void finish_item(const Dev& d, const Consts& c, int LJ, int jsub,
                                             int slice, int n_act, ILane& I, double bx, double by,
                                             double bz, double bvx, double bvy, double bvz) {
-  for (int off = LJ >> 1; off > 0; off >>= 1) {
+  {
+    double v[6 * kIPerLane];
 #pragma unroll
     for (int q = 0; q < kIPerLane; ++q) {
-      I.A[q].ax += shfl_xor_d(I.A[q].ax, off);
-      I.A[q].ay += shfl_xor_d(I.A[q].ay, off);
-      I.A[q].az += shfl_xor_d(I.A[q].az, off);
-      I.A[q].jx += shfl_xor_d(I.A[q].jx, off);
-      I.A[q].jy += shfl_xor_d(I.A[q].jy, off);
-      I.A[q].jz += shfl_xor_d(I.A[q].jz, off);
+      v[6 * q + 0] = I.A[q].ax; v[6 * q + 1] = I.A[q].ay; v[6 * q + 2] = I.A[q].az;
+      v[6 * q + 3] = I.A[q].jx; v[6 * q + 4] = I.A[q].jy; v[6 * q + 5] = I.A[q].jz;
+    }
+    group_sum(v, LJ);
+#pragma unroll
+    for (int q = 0; q < kIPerLane; ++q) {
+      I.A[q].ax = v[6 * q + 0]; I.A[q].ay = v[6 * q + 1]; I.A[q].az = v[6 * q + 2];
+      I.A[q].jx = v[6 * q + 3]; I.A[q].jy = v[6 * q + 4]; I.A[q].jz = v[6 * q + 5];
     }
   }
   if (kCentral && slice == 0 && jsub == 0) {
@@ -420,7 +476,7 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Consts c) {
 // memory round trip instead of s dependent ones. All lanes of the wave must
 // call it (valid == false contributes zeros).
 __device__ __forceinline__ void reduce_slices(const double* __restrict__ part, int s, int n_act,
-                                              int k, int L, int r, bool valid, double f[6]) {
+                                              int k, int L, int r, bool valid, double (&f)[6]) {
 #pragma unroll
   for (int q = 0; q < 6; ++q) f[q] = 0.0;
   if (valid) {
@@ -430,10 +486,7 @@ __device__ __forceinline__ void reduce_slices(const double* __restrict__ part, i
       for (int q = 0; q < 6; ++q) f[q] += o[(size_t)q * n_act];
     }
   }
-  for (int off = L >> 1; off > 0; off >>= 1) {
-#pragma unroll
-    for (int q = 0; q < 6; ++q) f[q] += shfl_xor_d(f[q], off);
-  }
+  group_sum(f, L);
 }
 
 // Workgroup-local bookkeeping, flushed to the Sched record with one atomic
