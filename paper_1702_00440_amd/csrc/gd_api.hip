@@ -143,6 +143,8 @@ Consts make_consts(const gd_params* p, int64_t n, int kmax) {
   c.kmax = kmax;
   c.dt_min = p->dt_min;
   c.dt_max = p->dt_max;
+  c.inv_dt_min = 1.0 / p->dt_min;
+  c.inv_dt_max = 1.0 / p->dt_max;
   c.eta = p->eta;
   c.eps2 = p->eps * p->eps;
   c.bh = (int)p->bh_index;

@@ -159,6 +159,7 @@ struct Consts {
   int bh;            // index of the central particle, -1 if none
   int mixed;         // 1: pair arithmetic in mixed precision (GD_FLAG_MIXED)
   double dt_min, dt_max, eta, eps2, eps2_bh;
+  double inv_dt_min, inv_dt_max;  // exact reciprocals (powers of two)
 };
 
 // Lanes the corrector gives one active particle: one per j slice of the

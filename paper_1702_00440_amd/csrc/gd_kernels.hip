@@ -163,12 +163,13 @@ __device__ __forceinline__ void group_sum(double (&v)[kN], int g) {
 // Smallest k >= 0 with dt_max / 2^k <= dtstar; kmax + 1 when even dt_min is
 // too large (the caller clamps and counts); 0 when dtstar is not a number
 // below dt_max (including +inf and NaN). With dtstar / dt_max = f 2^e,
-// f in [0.5, 1), the answer is exactly 1 - e.
-__device__ __forceinline__ int level_for(double dtstar, double dt_max, int kmax) {
+// f in [0.5, 1), the answer is exactly 1 - e. dt_max is a power of two, so
+// the quotient is the exact product with inv_dt_max = 1 / dt_max.
+__device__ __forceinline__ int level_for(double dtstar, double dt_max, double inv_dt_max, int kmax) {
   if (!(dtstar < dt_max)) return 0;
   if (!(dtstar > 0.0)) return kmax + 1;
   int e;
-  (void)frexp(dtstar / dt_max, &e);
+  (void)frexp(dtstar * inv_dt_max, &e);
   return min(1 - e, kmax + 1);
 }
 
@@ -567,14 +568,18 @@ __device__ __forceinline__ void correct_body(const Dev& d, const Consts& c, int 
     if (r != 0 || !valid) continue;
     if (!finite6(f)) bk.bad = 1;
 
+    // h and its powers are powers of two: dividing by h^2 and h^3 is the exact
+    // product with their reciprocals (from 1 / dt_min, scaled by 2^(lv - kmax)).
     const double h = (double)(1LL << (c.kmax - lv)) * c.dt_min;
     const double h2 = h * h, h3 = h2 * h;
+    const double ih = ldexp(c.inv_dt_min, lv - c.kmax);
+    const double ih2 = ih * ih, ih3 = ih2 * ih;
     double a2[3], a3[3], a2e[3], xn[3], vn[3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
       const double da = a0[q] - f[q];
-      a2[q] = (-6.0 * da - h * (4.0 * j0[q] + 2.0 * f[3 + q])) / h2;
-      a3[q] = (12.0 * da + 6.0 * h * (j0[q] + f[3 + q])) / h3;
+      a2[q] = (-6.0 * da - h * (4.0 * j0[q] + 2.0 * f[3 + q])) * ih2;
+      a3[q] = (12.0 * da + 6.0 * h * (j0[q] + f[3 + q])) * ih3;
       xn[q] = xp[q] + a2[q] * (h2 * h2) / 24.0 + a3[q] * (h2 * h3) / 120.0;
       vn[q] = vp[q] + a2[q] * h3 / 6.0 + a3[q] * (h2 * h2) / 24.0;
       a2e[q] = a2[q] + h * a3[q];
@@ -584,7 +589,7 @@ __device__ __forceinline__ void correct_body(const Dev& d, const Consts& c, int 
     const double na2 = norm3(a2e[0], a2e[1], a2e[2]);
     const double na3 = norm3(a3[0], a3[1], a3[2]);
     const double dtstar = sqrt(c.eta * (na1 * na2 + nj1 * nj1) / (nj1 * na3 + na2 * na2));
-    const int kc = level_for(dtstar, c.dt_max, c.kmax);
+    const int kc = level_for(dtstar, c.dt_max, c.inv_dt_max, c.kmax);
     int nl;
     if (kc >= lv) {
       nl = kc;
@@ -641,7 +646,7 @@ __global__ __launch_bounds__(kBlock) void k_init_dt(Dev d, Consts c) {
     if (r != 0 || !valid) continue;
     if (!finite6(f)) bk.bad = 1;
     const double dtstar = c.eta * norm3(f[0], f[1], f[2]) / norm3(f[3], f[4], f[5]);
-    int nl = level_for(dtstar, c.dt_max, c.kmax);
+    int nl = level_for(dtstar, c.dt_max, c.inv_dt_max, c.kmax);
     if (nl > c.kmax) {
       nl = c.kmax;
       atomicAdd(&bk.clamp, 1);
