@@ -147,7 +147,7 @@ struct Dev {
   double *ix, *iy, *iz, *ivx, *ivy, *ivz;  // predicted state of the active list, by position
   double *iax, *iay, *iaz, *ijx, *ijy, *ijz;  // a, jerk at t_i of the active list, by position
   int* ilev;                               // level of the active list, by position
-  double* part;                            // [s][6][n_act] partial forces
+  double* part;                            // [6][n_act][s] partial forces
   double* ebuf;                            // energy partials [kEnergyGrid][3] + result [3]
 };
 

@@ -270,7 +270,8 @@ __device__ __forceinline__ Plan make_plan_wave(int n_act, int n, int lane) {
 //   - j particles of the slice go through LDS in tiles of kTileJ, loaded
 //     with coalesced SoA reads and prefetched into registers one tile ahead;
 //   - the LJ lanes of one i are reduced with a fixed xor butterfly, and each
-//     slice writes its partial sum to part[slice][component][position].
+//     slice writes its partial sum to part[component][position][slice], so
+//     that the slices of one particle are contiguous for the reduction.
 // The slices of a particle are summed afterwards by the kernel that consumes
 // the force (corrector, initial steps, or output), in an order that depends
 // only on (n_act, n).
@@ -336,8 +337,9 @@ __device__ __forceinline__ void tile_pairs(const double (*sj)[kTileJ], int cnt, 
 // bx.. its predicted state), then the slice partials by list position.
 template <bool kCentral>
 __device__ __forceinline__ void finish_item(const Dev& d, const Consts& c, int LJ, int jsub,
-                                            int slice, int n_act, ILane& I, double bx, double by,
-                                            double bz, double bvx, double bvy, double bvz) {
+                                            int slice, int s, int n_act, ILane& I, double bx,
+                                            double by, double bz, double bvx, double bvy,
+                                            double bvz) {
   {
     double v[6 * kIPerLane];
 #pragma unroll
@@ -365,13 +367,15 @@ __device__ __forceinline__ void finish_item(const Dev& d, const Consts& c, int L
 #pragma unroll
     for (int q = 0; q < kIPerLane; ++q) {
       if (I.pos[q] < n_act) {
-        double* o = d.part + (size_t)slice * 6 * n_act + I.pos[q];
-        o[0 * (size_t)n_act] = I.A[q].ax;
-        o[1 * (size_t)n_act] = I.A[q].ay;
-        o[2 * (size_t)n_act] = I.A[q].az;
-        o[3 * (size_t)n_act] = I.A[q].jx;
-        o[4 * (size_t)n_act] = I.A[q].jy;
-        o[5 * (size_t)n_act] = I.A[q].jz;
+        // part[component][position][slice]
+        double* o = d.part + (size_t)I.pos[q] * s + slice;
+        const size_t cs = (size_t)n_act * s;
+        o[0 * cs] = I.A[q].ax;
+        o[1 * cs] = I.A[q].ay;
+        o[2 * cs] = I.A[q].az;
+        o[3 * cs] = I.A[q].jx;
+        o[4 * cs] = I.A[q].jy;
+        o[5 * cs] = I.A[q].jz;
       }
     }
   }
@@ -458,7 +462,7 @@ __device__ __forceinline__ void force_body(const Dev& d, const Consts& c, int bl
       bx = px[b]; by = py[b]; bz = pz[b];
       bvx = pvx[b]; bvy = pvy[b]; bvz = pvz[b];
     }
-    finish_item<kCentral>(d, c, LJ, jsub, slice, n_act, I, bx, by, bz, bvx, bvy, bvz);
+    finish_item<kCentral>(d, c, LJ, jsub, slice, p.s, n_act, I, bx, by, bz, bvx, bvy, bvz);
   }
 }
 
@@ -471,8 +475,9 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Consts c) {
 // Slice reduction and per-particle finishing
 // ---------------------------------------------------------------------------
 
-// The s slice partials of active position k, summed by the L consecutive
-// lanes of a group (lane r takes slices r, r + L, ...) and combined by a
+// The s slice partials of active position k (contiguous in
+// part[component][position][slice]), summed by the L consecutive lanes of a
+// group (lane r takes slices r, r + L, ...: coalesced) and combined by a
 // fixed xor butterfly: every lane of the group ends with the total. One
 // memory round trip instead of s dependent ones. All lanes of the wave must
 // call it (valid == false contributes zeros).
@@ -481,10 +486,11 @@ __device__ __forceinline__ void reduce_slices(const double* __restrict__ part, i
 #pragma unroll
   for (int q = 0; q < 6; ++q) f[q] = 0.0;
   if (valid) {
+    const size_t cs = (size_t)n_act * s;
+    const double* o = part + (size_t)k * s;
     for (int sl = r; sl < s; sl += L) {
-      const double* o = part + (size_t)sl * 6 * n_act + k;
 #pragma unroll
-      for (int q = 0; q < 6; ++q) f[q] += o[(size_t)q * n_act];
+      for (int q = 0; q < 6; ++q) f[q] += o[q * cs + sl];
     }
   }
   group_sum(f, L);
