@@ -19,7 +19,9 @@ The force kernel's per-launch durations come from HIP events that record
 each launch's own start and end (hipExtLaunchKernelGGL) during one more
 integration of the same workload right after the timed steps; in that pass
 the steps are launched directly rather than replayed from a graph, which
-changes the gaps between kernels but not the kernels.
+changes the gaps between kernels but not the kernels. The same pass splits
+them by block size (force_by_n_act), and the roofline line also gives the
+fraction reached by the launches with N_act >= 4096.
 """
 import argparse
 import json
@@ -191,11 +193,23 @@ def main():
     gpu_ms = ev0.elapsed_time(ev1)
     elapsed = max(wall, gpu_ms / 1e3)
     prof = {"force_ms": 0.0, "launches": 0, "pairs": 0}
+    buckets = []
     if not args.no_profile:
         g.gd_profile_force(ctx, True)
         one_step()
         prof = g.gd_profile_get(ctx)
+        buckets = g.gd_profile_buckets(ctx)
         g.gd_profile_force(ctx, False)
+    by_nact = []
+    for b in buckets:
+        if b["launches"] == 0:
+            continue
+        sec = b["force_ms"] / 1e3
+        tf = FLOPS_PER_PAIR * b["pairs"] / sec / 1e12 if sec > 0 else 0.0
+        by_nact.append({"n_act_min": b["n_act_min"], "n_act_max": b["n_act_max"], "launches": b["launches"],
+                        "avg_launch_us": sec / b["launches"] * 1e6, "pairs_per_s": b["pairs"] / sec if sec > 0 else 0.0,
+                        "achieved_tflops": tf, "frac": tf / PEAK_FP64_VECTOR_TFLOPS})
+    large = [b for b in by_nact if b["n_act_min"] >= 4096]
     launches = max(prof["launches"], 1)
     avg_s = prof["force_ms"] / 1e3 / launches
     flops_per_launch = FLOPS_PER_PAIR * prof["pairs"] / launches
@@ -236,7 +250,9 @@ def main():
             "launches": prof["launches"],
             "avg_launch_us": avg_s * 1e6,
             "flops_per_launch": flops_per_launch,
+            "frac_n_act_ge_4096": large[0]["frac"] if large else None,
         },
+        "force_by_n_act": by_nact,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

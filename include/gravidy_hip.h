@@ -134,6 +134,19 @@ gd_status gd_profile_force(gd_ctx* c, int enable);
 gd_status gd_profile_get(gd_ctx* c, double* force_ms, int64_t* launches, int64_t* pairs);
 
 /*
+ * The same force-launch timing split by block size: bucket b holds the
+ * launches with n_act_min[b] <= N_act < n_act_min[b + 1] (the last bucket is
+ * open), with N_act recorded on the device after each timed step. Host
+ * outputs of GD_PROFILE_BUCKETS entries each (any may be NULL): the lower
+ * edges (1, 2, 8, 64, 1024, 4096), the summed milliseconds, the number of
+ * launches and their pair interactions. Counters restart with
+ * gd_profile_force.
+ */
+#define GD_PROFILE_BUCKETS 6
+gd_status gd_profile_buckets(gd_ctx* c, int64_t* n_act_min, double* force_ms, int64_t* launches,
+                             int64_t* pairs);
+
+/*
  * Prediction of all particles (Sec. 2.4, steps 5 and 7(a)).
  * t == NULL: find the next block time t_next (the earliest t_i + dt_i),
  * mark the active particles (t_i + dt_i == t_next), and predict every particle

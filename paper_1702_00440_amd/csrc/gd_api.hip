@@ -26,6 +26,15 @@ using namespace gd;
 namespace {
 
 constexpr int kGraphSteps = 64;  // block steps per captured graph
+// Force-timing buckets by N_act: lower edges (the last bucket is open).
+constexpr int kProfBuckets = GD_PROFILE_BUCKETS;
+constexpr long long kProfEdges[kProfBuckets] = {1, 2, 8, 64, 1024, 4096};
+
+int prof_bucket(long long n_act) {
+  int b = 0;
+  while (b + 1 < kProfBuckets && n_act >= kProfEdges[b + 1]) ++b;
+  return b;
+}
 
 enum Phase { kIdle = 0, kPredictedAuto = 1, kPredictedExplicit = 2, kForcedAuto = 3, kForcedExplicit = 4 };
 
@@ -36,7 +45,7 @@ size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 // Byte offsets of every array in the workspace.
 struct Layout {
   size_t sc, m, jm, x[3], v[3], a[3], j[3], p[3], pv[3], tick, lev, active, ip[3], ipv[3], ia[3], ij[3], ilev,
-      part, ebuf, total;
+      part, ebuf, nact_log, total;
 };
 
 Layout make_layout(long long n) {
@@ -68,6 +77,7 @@ Layout make_layout(long long n) {
   L.part = take(sizeof(double) * 6 * (size_t)partial_rows(n));
   const long long eitems = std::max<long long>((n + kBlock - 1) / kBlock, kEnergyGrid);
   L.ebuf = take(sizeof(double) * 3 * (size_t)(eitems + 1));
+  L.nact_log = take(sizeof(int) * 72);
   L.total = off;
   return L;
 }
@@ -109,6 +119,7 @@ Dev carve(void* workspace, const Layout& L) {
   d.ilev = (int*)(w + L.ilev);
   d.part = (double*)(w + L.part);
   d.ebuf = (double*)(w + L.ebuf);
+  d.nact_log = (int*)(w + L.nact_log);
   return d;
 }
 
@@ -168,6 +179,9 @@ struct gd_ctx {
   hipEvent_t ev_s[kGraphSteps + 1] = {}, ev_e[kGraphSteps + 1] = {};
   double prof_ms = 0.0;
   long long prof_launches = 0, prof_pairs = 0;
+  double bucket_ms[GD_PROFILE_BUCKETS] = {};
+  long long bucket_launches[GD_PROFILE_BUCKETS] = {}, bucket_pairs[GD_PROFILE_BUCKETS] = {};
+  int* h_nact = nullptr;    // pinned host copy of the N_act log
   Sched* h_sc = nullptr;    // pinned host mirror of the device record
   double* h_e = nullptr;    // pinned host energy result (3 doubles)
   double* d_eres = nullptr; // device energy result
@@ -265,6 +279,10 @@ gd_status initialise(gd_ctx* c, const double* m, const double* x, const double* 
     c->prof_ms += ms;
     c->prof_launches += 1;
     c->prof_pairs += c->n * c->n;
+    const int b = prof_bucket(c->n);
+    c->bucket_ms[b] += ms;
+    c->bucket_launches[b] += 1;
+    c->bucket_pairs[b] += c->n * c->n;
   }
   double e[3];
   GD_TRY(energy_now(c, 0, e));
@@ -347,10 +365,30 @@ gd_status gd_profile_force(gd_ctx* c, int enable) {
     }
     c->ev_ready = true;
   }
+  if (enable && !c->h_nact)
+    GD_TRY(c->hip(hipHostMalloc((void**)&c->h_nact, sizeof(int) * kGraphSteps, hipHostMallocDefault),
+                  "pinned alloc"));
   c->prof = enable != 0;
   c->prof_ms = 0.0;
   c->prof_launches = 0;
   c->prof_pairs = 0;
+  for (int b = 0; b < kProfBuckets; ++b) {
+    c->bucket_ms[b] = 0.0;
+    c->bucket_launches[b] = 0;
+    c->bucket_pairs[b] = 0;
+  }
+  return GD_OK;
+}
+
+gd_status gd_profile_buckets(gd_ctx* c, int64_t* n_act_min, double* force_ms, int64_t* launches,
+                             int64_t* pairs) {
+  if (!c) return GD_EINVAL;
+  for (int b = 0; b < kProfBuckets; ++b) {
+    if (n_act_min) n_act_min[b] = kProfEdges[b];
+    if (force_ms) force_ms[b] = c->bucket_ms[b];
+    if (launches) launches[b] = c->bucket_launches[b];
+    if (pairs) pairs[b] = c->bucket_pairs[b];
+  }
   return GD_OK;
 }
 
@@ -454,7 +492,13 @@ gd_status gd_step_to(gd_ctx* c, double t_end, gd_stats* st) {
     GD_TRY(c->hip(launch_set_tend(c->d, chunk_end, c->stream), "prepare"));
     for (;;) {
       if (c->prof) {
-        for (int k = 0; k < kGraphSteps; ++k) GD_TRY(enqueue_step(c, c->stream, c->ev_s[k], c->ev_e[k]));
+        for (int k = 0; k < kGraphSteps; ++k) {
+          GD_TRY(enqueue_step(c, c->stream, c->ev_s[k], c->ev_e[k]));
+          GD_TRY(c->hip(launch_log_nact(c->d, c->d.nact_log + k, c->stream), "log kernel"));
+        }
+        GD_TRY(c->hip(hipMemcpyAsync(c->h_nact, c->d.nact_log, sizeof(int) * kGraphSteps,
+                                     hipMemcpyDeviceToHost, c->stream),
+                      "read log"));
       } else {
         GD_TRY(c->hip(hipGraphLaunch(c->graph, c->stream), "graph launch"));
       }
@@ -467,6 +511,10 @@ gd_status gd_step_to(gd_ctx* c, double t_end, gd_stats* st) {
           float ms = 0.f;
           GD_TRY(c->hip(hipEventElapsedTime(&ms, c->ev_s[k], c->ev_e[k]), "event time"));
           c->prof_ms += ms;
+          const int b = prof_bucket(c->h_nact[k]);
+          c->bucket_ms[b] += ms;
+          c->bucket_launches[b] += 1;
+          c->bucket_pairs[b] += (long long)c->h_nact[k] * c->n;
         }
         c->prof_launches += ran;
         c->prof_pairs += c->h_sc->pairs - pairs_before;
@@ -580,6 +628,7 @@ void gd_destroy(gd_ctx* c) {
   if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
   if (c->h_sc) (void)hipHostFree(c->h_sc);
   if (c->h_e) (void)hipHostFree(c->h_e);
+  if (c->h_nact) (void)hipHostFree(c->h_nact);
   delete c;
 }
 

@@ -149,6 +149,7 @@ struct Dev {
   int* ilev;                               // level of the active list, by position
   double* part;                            // [6][n_act][s] partial forces
   double* ebuf;                            // energy partials [kEnergyGrid][3] + result [3]
+  int* nact_log;                           // force-timing pass: N_act of each timed step
 };
 
 struct Consts {
@@ -232,6 +233,8 @@ hipError_t launch_predict(const Dev& d, const Consts& c, int mode, double t_expl
 hipError_t launch_force(const Dev& d, const Consts& c, hipStream_t s, hipEvent_t ev_start = nullptr,
                         hipEvent_t ev_stop = nullptr);
 hipError_t launch_correct(const Dev& d, const Consts& c, hipStream_t s);
+// Copies the N_act of the step in flight (0 if it was skipped) to *out.
+hipError_t launch_log_nact(const Dev& d, int* out, hipStream_t s);
 hipError_t launch_init_dt(const Dev& d, const Consts& c, hipStream_t s);
 hipError_t launch_reduce_out(const Dev& d, const Consts& c, double* acc, double* jerk, hipStream_t s);
 hipError_t launch_energy(const Dev& d, const Consts& c, int unsoft, hipStream_t s);

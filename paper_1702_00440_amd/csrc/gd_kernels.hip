@@ -1005,6 +1005,12 @@ __global__ void k_reset_sched(Sched* __restrict__ sc, long long t_now) {
   if (blockIdx.x == 0 && threadIdx.x <= kMaxLevels) sc->hist[threadIdx.x] = 0;
 }
 
+// N_act of the step in flight, for the force-timing pass (0 when the step was
+// skipped because the stop time was reached).
+__global__ void k_log_nact(const Sched* __restrict__ sc, int* __restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *out = sc->done ? 0 : sc->n_act;
+}
+
 // Prepares a sequence of automatic steps: sets the stop time and clears the
 // compaction counter.
 __global__ void k_set_tend(Sched* __restrict__ sc, long long t_end) {
@@ -1422,6 +1428,11 @@ hipError_t launch_energy(const Dev& d, const Consts& c, int unsoft, hipStream_t 
 
 hipError_t launch_set_tend(const Dev& d, long long t_end, hipStream_t s) {
   hipLaunchKernelGGL(k_set_tend, dim3(1), dim3(64), 0, s, d.sc, t_end);
+  return hipGetLastError();
+}
+
+hipError_t launch_log_nact(const Dev& d, int* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_log_nact, dim3(1), dim3(64), 0, s, d.sc, out);
   return hipGetLastError();
 }
 

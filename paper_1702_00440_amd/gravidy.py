@@ -63,6 +63,8 @@ def library():
     lib.gd_reinit.argtypes = [_VP, _VP, _VP, _VP]
     lib.gd_profile_force.argtypes = [_VP, C.c_int]
     lib.gd_profile_get.argtypes = [_VP, C.POINTER(C.c_double), C.POINTER(i64), C.POINTER(i64)]
+    lib.gd_profile_buckets.argtypes = [_VP, C.POINTER(i64), C.POINTER(C.c_double), C.POINTER(i64),
+                                       C.POINTER(i64)]
     lib.gd_predict.argtypes = [_VP, C.POINTER(C.c_double)]
     lib.gd_force.argtypes = [_VP, _VP, i64, _VP, _VP]
     lib.gd_active.argtypes = [_VP, _VP, C.POINTER(i64)]
@@ -75,7 +77,7 @@ def library():
     lib.gd_diagnostics.argtypes = [_VP, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_double),
                                    C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(i64), C.c_int32]
     lib.gd_diagnostics.restype = st
-    for name in ["gd_workspace_bytes", "gd_init", "gd_reinit", "gd_profile_force", "gd_profile_get", "gd_predict", "gd_force", "gd_active", "gd_correct",
+    for name in ["gd_workspace_bytes", "gd_init", "gd_reinit", "gd_profile_force", "gd_profile_get", "gd_profile_buckets", "gd_predict", "gd_force", "gd_active", "gd_correct",
                  "gd_step_to", "gd_energy", "gd_get_state", "gd_set_state", "gd_stats_get"]:
         getattr(lib, name).restype = st
     lib.gd_pool_arena_bytes.argtypes = [C.c_int32, C.POINTER(i64), C.c_int32, C.POINTER(C.c_size_t)]
@@ -171,6 +173,22 @@ def gd_profile_get(ctx) -> dict:
     ms, launches, pairs = C.c_double(), C.c_int64(), C.c_int64()
     _check(library().gd_profile_get(ctx, C.byref(ms), C.byref(launches), C.byref(pairs)), ctx)
     return {"force_ms": ms.value, "launches": int(launches.value), "pairs": int(pairs.value)}
+
+
+GD_PROFILE_BUCKETS = 6
+
+
+def gd_profile_buckets(ctx) -> list:
+    """Force-launch timing by block size: one dict per N_act bucket."""
+    nb = GD_PROFILE_BUCKETS
+    lo, ms, launches, pairs = (C.c_int64 * nb)(), (C.c_double * nb)(), (C.c_int64 * nb)(), (C.c_int64 * nb)()
+    _check(library().gd_profile_buckets(ctx, lo, ms, launches, pairs), ctx)
+    out = []
+    for b in range(nb):
+        hi = int(lo[b + 1]) - 1 if b + 1 < nb else None
+        out.append({"n_act_min": int(lo[b]), "n_act_max": hi, "force_ms": ms[b], "launches": int(launches[b]),
+                    "pairs": int(pairs[b])})
+    return out
 
 
 def gd_predict(ctx, t: float | None = None) -> None:

@@ -256,6 +256,17 @@ def test_reinit_matches_init_and_profiles_force():
     assert prof["launches"] == st["block_steps"] + 1
     assert prof["pairs"] == st["pair_interactions"] + n * n
     assert prof["force_ms"] > 0
+    # the same launches split by N_act: bucket sums equal the totals
+    bk = g.gd_profile_buckets(a.ctx)
+    assert [u["n_act_min"] for u in bk] == [1, 2, 8, 64, 1024, 4096]
+    assert sum(u["launches"] for u in bk) == prof["launches"]
+    assert sum(u["pairs"] for u in bk) == prof["pairs"]
+    assert sum(u["force_ms"] for u in bk) == pytest.approx(prof["force_ms"], rel=1e-9)
+    assert bk[4]["launches"] >= 1  # the initial force, N_act = 1024
+    for u in bk:
+        if u["launches"]:
+            lo, hi = u["n_act_min"], u["n_act_max"] or n
+            assert lo * n * u["launches"] <= u["pairs"] <= hi * n * u["launches"]
     g.gd_step_to(b.ctx, 0.125)
     for u, w in zip(a.state()[:6], b.state()[:6]):
         np.testing.assert_array_equal(host(u), host(w))
