@@ -270,8 +270,9 @@ __device__ __forceinline__ Plan make_plan_wave(int n_act, int n, int lane) {
 //   - j particles of the slice go through LDS in tiles of kTileJ, loaded
 //     with coalesced SoA reads and prefetched into registers one tile ahead;
 //   - the LJ lanes of one i are reduced with a fixed xor butterfly, and each
-//     slice writes its partial sum to part[component][position][slice], so
-//     that the slices of one particle are contiguous for the reduction.
+//     slice writes its partial sum to part[component][position][slot], so
+//     that the slices of one particle are contiguous for the reduction
+//     (slice_slot keeps the slices that one XCD computes next to each other).
 // The slices of a particle are summed afterwards by the kernel that consumes
 // the force (corrector, initial steps, or output), in an order that depends
 // only on (n_act, n).
@@ -332,6 +333,14 @@ __device__ __forceinline__ void tile_pairs(const double (*sj)[kTileJ], int cnt, 
   }
 }
 
+// Storage slot of slice sl among the s slices of one particle. When s is a
+// multiple of 8, item and workgroup index agree mod 8, so slice sl runs on
+// XCD sl % 8; its slices are stored together, and each XCD's L2 writes back
+// whole sectors instead of 8-byte pieces of lines that all eight share.
+__device__ __forceinline__ int slice_slot(int sl, int s) {
+  return (s & 7) ? sl : (sl & 7) * (s >> 3) + (sl >> 3);
+}
+
 // Butterfly over the LJ lanes that share an i (consecutive lanes), then the
 // central particle's pairs (softened with eps_bh, once per i, on slice 0;
 // bx.. its predicted state), then the slice partials by list position.
@@ -367,8 +376,8 @@ __device__ __forceinline__ void finish_item(const Dev& d, const Consts& c, int L
 #pragma unroll
     for (int q = 0; q < kIPerLane; ++q) {
       if (I.pos[q] < n_act) {
-        // part[component][position][slice]
-        double* o = d.part + (size_t)I.pos[q] * s + slice;
+        // part[component][position][slot]
+        double* o = d.part + (size_t)I.pos[q] * s + slice_slot(slice, s);
         const size_t cs = (size_t)n_act * s;
         o[0 * cs] = I.A[q].ax;
         o[1 * cs] = I.A[q].ay;
@@ -476,8 +485,8 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Consts c) {
 // ---------------------------------------------------------------------------
 
 // The s slice partials of active position k (contiguous in
-// part[component][position][slice]), summed by the L consecutive lanes of a
-// group (lane r takes slices r, r + L, ...: coalesced) and combined by a
+// part[component][position][slot]), summed by the L consecutive lanes of a
+// group (lane r takes slots r, r + L, ...: coalesced) and combined by a
 // fixed xor butterfly: every lane of the group ends with the total. One
 // memory round trip instead of s dependent ones. All lanes of the wave must
 // call it (valid == false contributes zeros).
