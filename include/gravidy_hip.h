@@ -317,6 +317,16 @@ const char* gd_pool_last_error(const gd_pool* pool);
 /* Statistics (host output). Synchronises. */
 gd_status gd_stats_get(gd_ctx* c, gd_stats* st);
 
+/*
+ * Histogram of the active-block sizes (the block steps of Sec. 2.2): counts[b]
+ * (host, GD_NACT_BINS entries) receives the number of block steps taken with
+ * 2^b <= N_act < 2^(b+1) since gd_init, gd_reinit or gd_set_state. The counts
+ * sum to gd_stats.block_steps. Synchronises.
+ * Errors: GD_EINVAL for NULL arguments; GD_EHIP.
+ */
+#define GD_NACT_BINS 32
+gd_status gd_nact_histogram(gd_ctx* c, int64_t* counts);
+
 /* Free the host-side context (not the workspace, which the caller owns). NULL is a no-op. */
 void gd_destroy(gd_ctx* c);
 

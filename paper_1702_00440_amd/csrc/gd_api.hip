@@ -604,6 +604,16 @@ gd_status gd_set_state(gd_ctx* c, const double* x, const double* v, const double
   return GD_OK;
 }
 
+static_assert(GD_NACT_BINS == kNactBins, "histogram bins of the header and the schedule record");
+
+gd_status gd_nact_histogram(gd_ctx* c, int64_t* counts) {
+  if (!c) return GD_EINVAL;
+  if (!counts) return c->fail(GD_EINVAL, "NULL argument");
+  GD_TRY(read_sched(c));
+  for (int b = 0; b < kNactBins; ++b) counts[b] = c->h_sc->nact_hist[b];
+  return GD_OK;
+}
+
 gd_status gd_stats_get(gd_ctx* c, gd_stats* st) {
   if (!c || !st) return GD_EINVAL;
   GD_TRY(read_sched(c));

@@ -34,6 +34,10 @@ constexpr int kEnergyGrid = 1024;
 // Maximum block-step level (dt = dt_max / 2^level).
 constexpr int kMaxLevels = 41;
 
+// Bins of the block-size histogram: bin b counts the block steps whose N_act
+// lies in [2^b, 2^(b+1)).
+constexpr int kNactBins = 32;
+
 // Mass fractions one diagnostics call can take.
 constexpr int kMaxDiagFractions = 32;
 
@@ -62,6 +66,7 @@ struct Sched {
   int nonfinite;     // set when a non-finite force or jerk is seen
   int bad_input;     // set by input / state validation
   long long block_steps, particle_steps, pairs, clamps;
+  long long nact_hist[kNactBins];  // block steps by floor(log2 N_act)
   Plan plan;                 // force decomposition of the step in flight
   int hist[kMaxLevels + 1];  // particles per level
 };

@@ -563,6 +563,7 @@ __device__ __forceinline__ void correct_body(const Dev& d, const Consts& c, int 
     sc->block_steps += 1;
     sc->particle_steps += n_act;
     sc->pairs += (long long)n_act * c.n;
+    if (n_act > 0) sc->nact_hist[31 - __clz(n_act)] += 1;
     sc->t_now = t_next;
     sc->cnt = 0;
   }
@@ -1012,6 +1013,7 @@ __global__ void k_reset_sched(Sched* __restrict__ sc, long long t_now) {
     sc->clamps = 0;
   }
   if (blockIdx.x == 0 && threadIdx.x <= kMaxLevels) sc->hist[threadIdx.x] = 0;
+  if (blockIdx.x == 0 && threadIdx.x < kNactBins) sc->nact_hist[threadIdx.x] = 0;
 }
 
 // N_act of the step in flight, for the force-timing pass (0 when the step was

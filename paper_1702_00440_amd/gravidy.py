@@ -74,11 +74,12 @@ def library():
     lib.gd_get_state.argtypes = [_VP, _VP, _VP, _VP, _VP, _VP, _VP, C.POINTER(C.c_double)]
     lib.gd_set_state.argtypes = [_VP, _VP, _VP, _VP, _VP, _VP, _VP, C.c_double]
     lib.gd_stats_get.argtypes = [_VP, C.POINTER(gd_stats)]
+    lib.gd_nact_histogram.argtypes = [_VP, C.POINTER(i64)]
     lib.gd_diagnostics.argtypes = [_VP, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_double),
                                    C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(i64), C.c_int32]
     lib.gd_diagnostics.restype = st
     for name in ["gd_workspace_bytes", "gd_init", "gd_reinit", "gd_profile_force", "gd_profile_get", "gd_profile_buckets", "gd_predict", "gd_force", "gd_active", "gd_correct",
-                 "gd_step_to", "gd_energy", "gd_get_state", "gd_set_state", "gd_stats_get"]:
+                 "gd_step_to", "gd_energy", "gd_get_state", "gd_set_state", "gd_stats_get", "gd_nact_histogram"]:
         getattr(lib, name).restype = st
     lib.gd_pool_arena_bytes.argtypes = [C.c_int32, C.POINTER(i64), C.c_int32, C.POINTER(C.c_size_t)]
     lib.gd_pool_create.argtypes = [C.POINTER(_VP), C.POINTER(gd_params), C.c_int32, _VP, C.c_size_t, _VP]
@@ -257,6 +258,17 @@ def gd_stats_get(ctx) -> dict:
     st = gd_stats()
     _check(library().gd_stats_get(ctx, C.byref(st)), ctx)
     return st.as_dict()
+
+
+GD_NACT_BINS = 32
+
+
+def gd_nact_histogram(ctx) -> list:
+    """Block steps since init / reinit / set_state by active-block size:
+    entry b counts the steps with 2^b <= N_act < 2^(b+1)."""
+    counts = (C.c_int64 * GD_NACT_BINS)()
+    _check(library().gd_nact_histogram(ctx, counts), ctx)
+    return [int(c) for c in counts]
 
 
 def gd_destroy(ctx) -> None:

@@ -135,3 +135,44 @@ def test_mixed_against_fp64_all_particles():
     assert ea.max() <= MIX_TOL
     assert np.percentile(ej, 99.9) <= MIX_TOL
     assert ej.max() <= 1e-5
+
+
+def test_mixed_replays_fp64_block_steps_imf():
+    """The mixed-precision workload (N = 262144, power-law IMF) replayed along
+    an FP64 run: before each of the first 256 block steps the mixed context
+    takes the FP64 context's state, so both predict the same j stream and
+    select the same active block; the mixed force of that block is then
+    compared with the FP64 one, row by row, with the bounds used for all
+    particles at t = 0."""
+    n = 262144
+    m, x, v = plummer_imf(n, 5)
+    ctx = {0: g.Cluster(m, x, v, device=DEV), MIXED: g.Cluster(m, x, v, device=DEV, flags=MIXED)}
+    out = {f: (torch.empty(n, 3, dtype=torch.float64, device=DEV),
+               torch.empty(n, 3, dtype=torch.float64, device=DEV),
+               torch.empty(n, dtype=torch.int32, device=DEV)) for f in ctx}
+    ea, ej, sizes = [], [], []
+    for step in range(256):
+        xs, vs, a, j, t_i, dt_i, t_now = ctx[0].state()
+        g.gd_set_state(ctx[MIXED].ctx, xs, vs, a, j, t_i, dt_i, t_now)
+        rows = {}
+        for f, cl in ctx.items():
+            acc, jrk, idx = out[f]
+            g.gd_predict(cl.ctx)
+            g.gd_force(cl.ctx, None, acc, jrk)
+            k = g.gd_active(cl.ctx, idx)
+            order = torch.argsort(idx[:k])
+            rows[f] = host(idx[:k][order]), host(acc[:k][order]), host(jrk[:k][order])
+        np.testing.assert_array_equal(rows[MIXED][0], rows[0][0])
+        ea.append(rel_err_rows(rows[MIXED][1], rows[0][1]))
+        ej.append(rel_err_rows(rows[MIXED][2], rows[0][2]))
+        sizes.append(len(rows[0][0]))
+        g.gd_correct(ctx[0].ctx)
+    for cl in ctx.values():
+        cl.close()
+    ea, ej = np.concatenate(ea), np.concatenate(ej)
+    print(f"256 replayed steps, {len(ea)} rows (N_act {min(sizes)}..{max(sizes)}): acc max {ea.max():.2e}; "
+          f"jerk p99.9 {np.percentile(ej, 99.9):.2e} max {ej.max():.2e}")
+    assert min(sizes) < max(sizes)
+    assert ea.max() <= MIX_TOL
+    assert np.percentile(ej, 99.9) <= MIX_TOL
+    assert ej.max() <= 1e-5

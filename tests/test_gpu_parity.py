@@ -298,6 +298,31 @@ def test_diagnostics_against_oracle(n):
     cl.close()
 
 
+def test_nact_histogram_against_oracle():
+    """Block steps by active-block size (bin b: 2^b <= N_act < 2^(b+1)) over
+    Plummer N = 1024 to t = 1/8 equal the histogram of the oracle's own
+    active sets, taken step by step; the counts sum to the block steps and
+    restart at zero with gd_set_state."""
+    n = 1024
+    m, x, v = plummer(n, 1)
+    cl = g.Cluster(m, x, v, eta=ETA, eps=EPS, device=DEV)
+    st = g.gd_step_to(cl.ctx, 0.125)
+    hist = g.gd_nact_histogram(cl.ctx)
+    ref = oracle.State(m, x, v, EPS, ETA, DTMAX, DTMIN, threads=8)
+    want = [0] * g.GD_NACT_BINS
+    steps = 0
+    while ref.t_now < 0.125:
+        want[len(ref.block_step()).bit_length() - 1] += 1
+        steps += 1
+    assert steps == st["block_steps"] == sum(hist)
+    assert hist == want
+    assert sum(1 for c in hist if c) >= 5  # the run spans several bins
+    xs, vs, a, j, t_i, dt_i, t_now = cl.state()
+    g.gd_set_state(cl.ctx, xs, vs, a, j, t_i, dt_i, t_now)
+    assert g.gd_nact_histogram(cl.ctx) == [0] * g.GD_NACT_BINS
+    cl.close()
+
+
 @pytest.mark.parametrize("dtmin_exp", [8, 10])
 def test_dt_min_clamps_against_oracle(dtmin_exp):
     """A coarse dt_min (2^-8, 2^-10) makes many steps clamp: the number of
