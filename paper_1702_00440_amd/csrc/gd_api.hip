@@ -162,6 +162,10 @@ Consts make_consts(const gd_params* p, int64_t n, int kmax) {
   c.eps2_bh = p->bh_index >= 0 ? p->eps_bh * p->eps_bh : c.eps2;
   launch_grids((int)n, &c.force_grid, &c.correct_grid);
   c.mixed = (p->flags & GD_FLAG_MIXED) ? 1 : 0;
+  const Plan p1 = make_plan(1, (int)n);
+  c.lj1 = p1.lj;
+  c.s1 = p1.s;
+  c.part_cs = partial_rows(n);
   return c;
 }
 

@@ -152,7 +152,7 @@ struct Dev {
   double *ix, *iy, *iz, *ivx, *ivy, *ivz;  // predicted state of the active list, by position
   double *iax, *iay, *iaz, *ijx, *ijy, *ijz;  // a, jerk at t_i of the active list, by position
   int* ilev;                               // level of the active list, by position
-  double* part;                            // [6][n_act][s] partial forces
+  double* part;                            // [6][partial_rows(n)]: position * s + slot
   double* ebuf;                            // energy partials [kEnergyGrid][3] + result [3]
   int* nact_log;                           // force-timing pass: N_act of each timed step
 };
@@ -166,6 +166,8 @@ struct Consts {
   int mixed;         // 1: pair arithmetic in mixed precision (GD_FLAG_MIXED)
   double dt_min, dt_max, eta, eps2, eps2_bh;
   double inv_dt_min, inv_dt_max;  // exact reciprocals (powers of two)
+  int lj1, s1;        // decomposition of a one-particle block: log2 lanes per i, j slices
+  long long part_cs;  // component stride of the partial-force buffer (partial_rows(n))
 };
 
 // Lanes the corrector gives one active particle: one per j slice of the

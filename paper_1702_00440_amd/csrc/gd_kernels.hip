@@ -376,9 +376,9 @@ __device__ __forceinline__ void finish_item(const Dev& d, const Consts& c, int L
 #pragma unroll
     for (int q = 0; q < kIPerLane; ++q) {
       if (I.pos[q] < n_act) {
-        // part[component][position][slot]
+        // part[component][position][slot], components part_cs apart
         double* o = d.part + (size_t)I.pos[q] * s + slice_slot(slice, s);
-        const size_t cs = (size_t)n_act * s;
+        const size_t cs = (size_t)c.part_cs;
         o[0 * cs] = I.A[q].ax;
         o[1 * cs] = I.A[q].ay;
         o[2 * cs] = I.A[q].az;
@@ -393,12 +393,7 @@ __device__ __forceinline__ void finish_item(const Dev& d, const Consts& c, int L
 template <bool kMaskSelf, bool kCentral, bool kMixed>
 __device__ __forceinline__ void force_body(const Dev& d, const Consts& c, int blk, int nblk) {
   const Sched* __restrict__ sc = d.sc;
-  if (sc->done) return;
-  const int n_act = sc->n_act;
-  if (n_act <= 0) return;
   const int n = c.n;
-  const Plan p = sc->plan;
-  if (blk >= p.items) return;
   const double* __restrict__ px = d.px;
   const double* __restrict__ py = d.py;
   const double* __restrict__ pz = d.pz;
@@ -411,24 +406,17 @@ __device__ __forceinline__ void force_body(const Dev& d, const Consts& c, int bl
 
   __shared__ double sj[7][kTileJ];
   const int tid = threadIdx.x;
-  const int LJ = 1 << p.lj;
-  const int jsub = tid & (LJ - 1);
-  const int ilane = tid >> p.lj;
-  const int ilanes = kBlock >> p.lj;
 
-  for (int item = blk; item < p.items; item += nblk) {
-    const int itile = item / p.s;
-    const int slice = item - itile * p.s;
-    const int j0 = slice * p.len;
-    const int j1 = min(n, j0 + p.len);
-
-    ILane I;
+  // The i particles of an item. The predicted state of the active list is
+  // stored by list position (one load level instead of an index gather).
+  // Positions past the list read entry kc instead: any entry in bounds
+  // serves, since their sums are never stored.
+  ILane I;
+  auto load_i = [&](int itile, int it, int ilane, int ilanes, int kc) {
 #pragma unroll
     for (int q = 0; q < kIPerLane; ++q) {
-      I.pos[q] = itile * p.it + ilane + q * ilanes;
-      // The predicted state of the active list is stored by list position
-      // (one load level instead of an index gather).
-      const int k = min(I.pos[q], n_act - 1);
+      I.pos[q] = itile * it + ilane + q * ilanes;
+      const int k = min(I.pos[q], kc);
       I.g[q] = (kMaskSelf || kCentral) ? d.active[k] : 0;
       // Softening enters only as the addend of r.r, so a per-i value costs
       // nothing: the central particle takes eps_bh for all of its pairs.
@@ -441,20 +429,54 @@ __device__ __forceinline__ void force_body(const Dev& d, const Consts& c, int bl
       I.vz[q] = d.ivz[k];
       I.A[q] = Acc6{0, 0, 0, 0, 0, 0};
     }
+  };
+  // Tile loads and LDS stores are lane-uniform (indices clamped into the
+  // slice, lanes past its end store a duplicate that is never read): the
+  // i loads are then drained on every path before the first tile, and the
+  // inner loop does not wait on the prefetch of the next tile.
+  static_assert(kTileJ == kBlock, "one j per thread per tile");
+  double rx = 0, ry = 0, rz = 0, rvx = 0, rvy = 0, rvz = 0, rm = 0;
+  auto load_tile = [&](int base, int j1) {
+    const int j = min(base + tid, j1 - 1);
+    rx = px[j]; ry = py[j]; rz = pz[j];
+    rvx = pvx[j]; rvy = pvy[j]; rvz = pvz[j];
+    rm = pm[j];
+  };
 
-    // Tile loads and LDS stores are lane-uniform (indices clamped into the
-    // slice, lanes past its end store a duplicate that is never read): the
-    // i loads above are then drained on every path before the first tile,
-    // and the inner loop does not wait on the prefetch of the next tile.
-    static_assert(kTileJ == kBlock, "one j per thread per tile");
-    double rx = 0, ry = 0, rz = 0, rvx = 0, rvy = 0, rvz = 0, rm = 0;
-    auto load_tile = [&](int base) {
-      const int j = min(base + tid, j1 - 1);
-      rx = px[j]; ry = py[j]; rz = pz[j];
-      rvx = pvx[j]; rvy = pvy[j]; rvz = pvz[j];
-      rm = pm[j];
-    };
-    if (j0 < j1) load_tile(j0);
+  // Small blocks share the decomposition of a one-particle block (lj1, s1),
+  // which n alone fixes: one i tile, whose items are the first s1
+  // workgroups. Those request their item before the schedule record is
+  // read, so that the two memory round trips overlap; a step with another
+  // decomposition loads its items afresh.
+  const bool spec = blk < c.s1;
+  if (spec) {
+    const int len1 = (n + c.s1 - 1) / c.s1;
+    const int j0 = blk * len1, j1 = min(n, j0 + len1);
+    load_i(0, (kBlock >> c.lj1) * kIPerLane, tid >> c.lj1, kBlock >> c.lj1, n - 1);
+    if (j0 < j1) load_tile(j0, j1);
+  }
+
+  if (sc->done) return;
+  const int n_act = sc->n_act;
+  if (n_act <= 0) return;
+  const Plan p = sc->plan;
+  if (blk >= p.items) return;
+  // Same lanes per i and slices: same tile size, slice length and item map.
+  const bool early = spec && p.lj == c.lj1 && p.s == c.s1;
+  const int LJ = 1 << p.lj;
+  const int jsub = tid & (LJ - 1);
+  const int ilane = tid >> p.lj;
+  const int ilanes = kBlock >> p.lj;
+
+  for (int item = blk; item < p.items; item += nblk) {
+    const int itile = item / p.s;
+    const int slice = item - itile * p.s;
+    const int j0 = slice * p.len;
+    const int j1 = min(n, j0 + p.len);
+    if (item != blk || !early) {
+      load_i(itile, p.it, ilane, ilanes, n_act - 1);
+      if (j0 < j1) load_tile(j0, j1);
+    }
     for (int jt = j0; jt < j1; jt += kTileJ) {
       const int cnt = min(kTileJ, j1 - jt);
       __syncthreads();
@@ -462,7 +484,7 @@ __device__ __forceinline__ void force_body(const Dev& d, const Consts& c, int bl
       sj[3][tid] = rvx; sj[4][tid] = rvy; sj[5][tid] = rvz;
       sj[6][tid] = rm;
       __syncthreads();
-      if (jt + kTileJ < j1) load_tile(jt + kTileJ);
+      if (jt + kTileJ < j1) load_tile(jt + kTileJ, j1);
       tile_pairs<kMaskSelf, kMixed>(sj, cnt, LJ, jsub, jt, c.eps2, I);
     }
     double bx = 0, by = 0, bz = 0, bvx = 0, bvy = 0, bvz = 0;
@@ -490,12 +512,11 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Consts c) {
 // fixed xor butterfly: every lane of the group ends with the total. One
 // memory round trip instead of s dependent ones. All lanes of the wave must
 // call it (valid == false contributes zeros).
-__device__ __forceinline__ void reduce_slices(const double* __restrict__ part, int s, int n_act,
+__device__ __forceinline__ void reduce_slices(const double* __restrict__ part, int s, long long cs,
                                               int k, int L, int r, bool valid, double (&f)[6]) {
 #pragma unroll
   for (int q = 0; q < 6; ++q) f[q] = 0.0;
   if (valid) {
-    const size_t cs = (size_t)n_act * s;
     const double* o = part + (size_t)k * s;
     for (int sl = r; sl < s; sl += L) {
 #pragma unroll
@@ -548,14 +569,48 @@ __device__ __forceinline__ bool finite6(const double f[6]) {
 // particle share the slice reduction and the first lane corrects.
 __device__ __forceinline__ void correct_body(const Dev& d, const Consts& c, int blk, int nblk) {
   Sched* __restrict__ sc = d.sc;
+  const int tid = threadIdx.x;
+  // Small blocks use the slice count of a one-particle block (s1, which n
+  // alone fixes) and fill at most its first i tile. The workgroups that hold
+  // those positions request their state, and their slice partials when one
+  // slot per lane covers them, before the schedule record is read, so that
+  // the two memory round trips overlap; a step with another layout loads
+  // afresh. Lanes past the list read entries in bounds (positions below n
+  // and below part_cs / s1, which every block with s1 slices satisfies).
+  const int L1 = correct_lanes(c.s1);
+  const int per1 = kBlock / L1;
+  const bool spec = blk * per1 < (kBlock >> c.lj1) * kIPerLane;
+  const bool one_slot = c.s1 <= L1;
+  int i = 0, lv = 0;
+  double a0[3] = {0.0, 0.0, 0.0}, j0[3] = {0.0, 0.0, 0.0};
+  double xp[3] = {0.0, 0.0, 0.0}, vp[3] = {0.0, 0.0, 0.0};
+  double g1[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (spec) {
+    const int r1 = tid & (L1 - 1);
+    const int kcap = (int)min((long long)c.n, c.part_cs / c.s1) - 1;
+    const int k1 = min(blk * per1 + tid / L1, kcap);
+    i = d.active[k1];
+    lv = d.ilev[k1];
+    a0[0] = d.iax[k1]; a0[1] = d.iay[k1]; a0[2] = d.iaz[k1];
+    j0[0] = d.ijx[k1]; j0[1] = d.ijy[k1]; j0[2] = d.ijz[k1];
+    xp[0] = d.ix[k1]; xp[1] = d.iy[k1]; xp[2] = d.iz[k1];
+    vp[0] = d.ivx[k1]; vp[1] = d.ivy[k1]; vp[2] = d.ivz[k1];
+    if (one_slot && r1 < c.s1) {
+      const double* o = d.part + (size_t)k1 * c.s1 + r1;
+#pragma unroll
+      for (int q = 0; q < 6; ++q) g1[q] = o[q * c.part_cs];
+    }
+  }
+
   if (sc->done) return;
   const int n_act = sc->n_act;
   const long long t_next = sc->t_next;
   const Plan p = sc->plan;
   const int L = correct_lanes(p.s);
   const int per_wg = kBlock / L;
-  const int tid = threadIdx.x;
   if (blk * per_wg >= n_act && blk != 0) return;
+  // Same slice count: same lanes per particle and the same positions.
+  const bool early = spec && p.s == c.s1;
   __shared__ LocalBook bk;
   book_init(bk, tid);
   __syncthreads();
@@ -572,15 +627,25 @@ __device__ __forceinline__ void correct_body(const Dev& d, const Consts& c, int 
     const int k = base + tid / L;
     const bool valid = k < n_act;
     const int kk = valid ? k : 0;
-    // Loads that do not depend on the reduction, issued with it.
-    const int i = d.active[kk];
-    const int lv = d.ilev[kk];
-    const double a0[3] = {d.iax[kk], d.iay[kk], d.iaz[kk]};
-    const double j0[3] = {d.ijx[kk], d.ijy[kk], d.ijz[kk]};
-    const double xp[3] = {d.ix[kk], d.iy[kk], d.iz[kk]};
-    const double vp[3] = {d.ivx[kk], d.ivy[kk], d.ivz[kk]};
+    const bool first = early && base == blk * per_wg;
+    if (!first) {
+      // Loads that do not depend on the reduction, issued with it.
+      i = d.active[kk];
+      lv = d.ilev[kk];
+      a0[0] = d.iax[kk]; a0[1] = d.iay[kk]; a0[2] = d.iaz[kk];
+      j0[0] = d.ijx[kk]; j0[1] = d.ijy[kk]; j0[2] = d.ijz[kk];
+      xp[0] = d.ix[kk]; xp[1] = d.iy[kk]; xp[2] = d.iz[kk];
+      vp[0] = d.ivx[kk]; vp[1] = d.ivy[kk]; vp[2] = d.ivz[kk];
+    }
     double f[6];
-    reduce_slices(d.part, p.s, n_act, k, L, r, valid, f);
+    if (first && one_slot) {
+      // The sum reduce_slices forms from the same one slot per lane.
+#pragma unroll
+      for (int q = 0; q < 6; ++q) f[q] = (valid && r < p.s) ? 0.0 + g1[q] : 0.0;
+      group_sum(f, L);
+    } else {
+      reduce_slices(d.part, p.s, c.part_cs, k, L, r, valid, f);
+    }
     if (r != 0 || !valid) continue;
     if (!finite6(f)) bk.bad = 1;
 
@@ -600,7 +665,7 @@ __device__ __forceinline__ void correct_body(const Dev& d, const Consts& c, int 
       vn[q] = vp[q] + a2[q] * h3 / 6.0 + a3[q] * (h2 * h2) / 24.0;
       a2e[q] = a2[q] + h * a3[q];
     }
-    const double na1 = norm3(f[0], f[1], f[2]);
+  const double na1 = norm3(f[0], f[1], f[2]);
     const double nj1 = norm3(f[3], f[4], f[5]);
     const double na2 = norm3(a2e[0], a2e[1], a2e[2]);
     const double na3 = norm3(a3[0], a3[1], a3[2]);
@@ -658,7 +723,7 @@ __global__ __launch_bounds__(kBlock) void k_init_dt(Dev d, Consts c) {
     const bool valid = k < n_act;
     const int i = d.active[valid ? k : 0];
     double f[6];
-    reduce_slices(d.part, p.s, n_act, k, L, r, valid, f);
+    reduce_slices(d.part, p.s, c.part_cs, k, L, r, valid, f);
     if (r != 0 || !valid) continue;
     if (!finite6(f)) bk.bad = 1;
     const double dtstar = c.eta * norm3(f[0], f[1], f[2]) / norm3(f[3], f[4], f[5]);
@@ -693,7 +758,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_out(Dev d, Consts c, double* 
     const int k = base + tid / L;
     const bool valid = k < n_act;
     double f[6];
-    reduce_slices(d.part, p.s, n_act, k, L, r, valid, f);
+    reduce_slices(d.part, p.s, c.part_cs, k, L, r, valid, f);
     if (r != 0 || !valid) continue;
     if (!finite6(f)) bad = true;
     if (acc) {
