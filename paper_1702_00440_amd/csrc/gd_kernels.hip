@@ -143,6 +143,39 @@ __device__ __forceinline__ void xor_add(double (&v)[kN]) {
   for (int k = 0; k < kN; ++k) v[k] += xor_partner_d<kOff>(v[k]);
 }
 
+// The pair (a, b) combined with the pair of lane (lane ^ kOff): lanes with
+// the kOff bit clear return a + a', lanes with it set b' + b (primes mark the
+// partner's values), so each lane of an exchanging pair keeps one of the two
+// sums. At offsets 16 and 32 one row swap per 32-bit word moves both halves
+// (v_permlane16/32_swap exchange the odd rows of their first operand with the
+// even rows of their second); smaller offsets send the half that the partner
+// keeps. IEEE addition commutes, so both forms give the same value.
+template <int kOff>
+__device__ __forceinline__ double split_add(double a, double b) {
+  if constexpr (kOff >= 16) {
+    const unsigned long long ua = (unsigned long long)__double_as_longlong(a);
+    const unsigned long long ub = (unsigned long long)__double_as_longlong(b);
+    const int alo = (int)(unsigned)ua, ahi = (int)(unsigned)(ua >> 32);
+    const int blo = (int)(unsigned)ub, bhi = (int)(unsigned)(ub >> 32);
+    auto swap = [](int x, int y) {
+      if constexpr (kOff == 16) return __builtin_amdgcn_permlane16_swap(x, y, false, false);
+      else return __builtin_amdgcn_permlane32_swap(x, y, false, false);
+    };
+    const auto lo = swap(alo, blo);
+    const auto hi = swap(ahi, bhi);
+    const double r0 = __longlong_as_double(
+        (long long)(((unsigned long long)(unsigned)hi[0] << 32) | (unsigned)lo[0]));
+    const double r1 = __longlong_as_double(
+        (long long)(((unsigned long long)(unsigned)hi[1] << 32) | (unsigned)lo[1]));
+    return r0 + r1;
+  } else {
+    const bool up = (threadIdx.x & kOff) != 0;
+    const double send = up ? a : b;
+    const double keep = up ? b : a;
+    return keep + xor_partner_d<kOff>(send);
+  }
+}
+
 // Sum of v over each aligned group of g consecutive lanes (g a power of two,
 // at most 64), left in every lane of the group: a butterfly with offsets
 // g/2, ..., 1 (one uniform branch per level).
@@ -154,6 +187,41 @@ __device__ __forceinline__ void group_sum(double (&v)[kN], int g) {
   if (g > 4) xor_add<4>(v);
   if (g > 2) xor_add<2>(v);
   if (g > 1) xor_add<1>(v);
+}
+
+// Acceleration and jerk (f[0..2], f[3..5]) summed over each aligned group of
+// kL consecutive lanes, left in every lane of the group: the first exchange
+// keeps the acceleration in the lower half of the group and the jerk in the
+// upper, a butterfly sums those 3 values over the half, and one more exchange
+// gives each lane the other half's totals.
+template <int kL>
+__device__ __forceinline__ void force_sums(double (&f)[6]) {
+  if constexpr (kL > 1) {
+    double t[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) t[k] = split_add<kL / 2>(f[k], f[3 + k]);
+    if constexpr (kL / 2 > 1) group_sum(t, kL / 2);
+    const bool lower = (threadIdx.x & (kL / 2)) == 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double o = xor_partner_d<kL / 2>(t[k]);
+      f[k] = lower ? t[k] : o;
+      f[3 + k] = lower ? o : t[k];
+    }
+  }
+}
+
+// force_sums for a group size known at run time (a power of two up to 64).
+__device__ __forceinline__ void force_sums(double (&f)[6], int L) {
+  switch (L) {
+    case 64: force_sums<64>(f); break;
+    case 32: force_sums<32>(f); break;
+    case 16: force_sums<16>(f); break;
+    case 8: force_sums<8>(f); break;
+    case 4: force_sums<4>(f); break;
+    case 2: force_sums<2>(f); break;
+    default: break;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -341,28 +409,33 @@ __device__ __forceinline__ int slice_slot(int sl, int s) {
   return (s & 7) ? sl : (sl & 7) * (s >> 3) + (sl >> 3);
 }
 
-// Butterfly over the LJ lanes that share an i (consecutive lanes), then the
-// central particle's pairs (softened with eps_bh, once per i, on slice 0;
-// bx.. its predicted state), then the slice partials by list position.
+// The 12 sums of a group of kLJ lanes that share two i (acceleration and
+// jerk of each) reduced over the group by halving: the first exchange keeps
+// the first i in the lower half of the group and the second in the upper
+// half, the next keeps the acceleration in the lower quarter of each half and
+// the jerk in the upper, and a butterfly sums the remaining 3 values over the
+// quarter. Every lane of quarter k ends with the totals of block k of 3.
+template <int kLJ>
+__device__ __forceinline__ void quarter_sums(const double (&v)[12], double (&t)[3]) {
+  double h[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) h[k] = split_add<kLJ / 2>(v[k], v[6 + k]);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) t[k] = split_add<kLJ / 4>(h[k], h[3 + k]);
+  if constexpr (kLJ / 8 >= 1) group_sum(t, kLJ / 4);
+}
+
+// Reduction over the LJ lanes that share an i (consecutive lanes), then the
+// slice partials by list position, stored by the first lane of each quarter
+// of the group. The central particle's pairs (softened with eps_bh, once per
+// i, on slice 0; bx.. its predicted state) are added to the first lane's
+// sums before the reduction.
 template <bool kCentral>
 __device__ __forceinline__ void finish_item(const Dev& d, const Consts& c, int LJ, int jsub,
                                             int slice, int s, int n_act, ILane& I, double bx,
                                             double by, double bz, double bvx, double bvy,
                                             double bvz) {
-  {
-    double v[6 * kIPerLane];
-#pragma unroll
-    for (int q = 0; q < kIPerLane; ++q) {
-      v[6 * q + 0] = I.A[q].ax; v[6 * q + 1] = I.A[q].ay; v[6 * q + 2] = I.A[q].az;
-      v[6 * q + 3] = I.A[q].jx; v[6 * q + 4] = I.A[q].jy; v[6 * q + 5] = I.A[q].jz;
-    }
-    group_sum(v, LJ);
-#pragma unroll
-    for (int q = 0; q < kIPerLane; ++q) {
-      I.A[q].ax = v[6 * q + 0]; I.A[q].ay = v[6 * q + 1]; I.A[q].az = v[6 * q + 2];
-      I.A[q].jx = v[6 * q + 3]; I.A[q].jy = v[6 * q + 4]; I.A[q].jz = v[6 * q + 5];
-    }
-  }
+  static_assert(kIPerLane == 2, "the reduction splits the sums of two i");
   if (kCentral && slice == 0 && jsub == 0) {
     const int b = c.bh;
     const double bm = d.m[b];
@@ -372,20 +445,28 @@ __device__ __forceinline__ void finish_item(const Dev& d, const Consts& c, int L
         pair_fp64(I.x[q], I.y[q], I.z[q], I.vx[q], I.vy[q], I.vz[q], bx, by, bz, bvx, bvy, bvz, bm,
                   c.eps2_bh, I.A[q]);
   }
-  if (jsub == 0) {
+  double v[12];
 #pragma unroll
-    for (int q = 0; q < kIPerLane; ++q) {
-      if (I.pos[q] < n_act) {
-        // part[component][position][slot], components part_cs apart
-        double* o = d.part + (size_t)I.pos[q] * s + slice_slot(slice, s);
-        const size_t cs = (size_t)c.part_cs;
-        o[0 * cs] = I.A[q].ax;
-        o[1 * cs] = I.A[q].ay;
-        o[2 * cs] = I.A[q].az;
-        o[3 * cs] = I.A[q].jx;
-        o[4 * cs] = I.A[q].jy;
-        o[5 * cs] = I.A[q].jz;
-      }
+  for (int q = 0; q < kIPerLane; ++q) {
+    v[6 * q + 0] = I.A[q].ax; v[6 * q + 1] = I.A[q].ay; v[6 * q + 2] = I.A[q].az;
+    v[6 * q + 3] = I.A[q].jx; v[6 * q + 4] = I.A[q].jy; v[6 * q + 5] = I.A[q].jz;
+  }
+  double t[3];
+  if (LJ == 64) quarter_sums<64>(v, t);
+  else if (LJ == 32) quarter_sums<32>(v, t);
+  else quarter_sums<16>(v, t);
+  const int quarter = LJ >> 2;
+  if ((jsub & (quarter - 1)) == 0) {
+    const int q = jsub >= 2 * quarter;           // which i
+    const int comp = (jsub & quarter) ? 3 : 0;  // acceleration or jerk
+    const int pos = q ? I.pos[1] : I.pos[0];
+    if (pos < n_act) {
+      // part[component][position][slot], components part_cs apart
+      const size_t cs = (size_t)c.part_cs;
+      double* o = d.part + (size_t)pos * s + slice_slot(slice, s) + comp * cs;
+      o[0 * cs] = t[0];
+      o[1 * cs] = t[1];
+      o[2 * cs] = t[2];
     }
   }
 }
@@ -508,10 +589,10 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Consts c) {
 
 // The s slice partials of active position k (contiguous in
 // part[component][position][slot]), summed by the L consecutive lanes of a
-// group (lane r takes slots r, r + L, ...: coalesced) and combined by a
-// fixed xor butterfly: every lane of the group ends with the total. One
-// memory round trip instead of s dependent ones. All lanes of the wave must
-// call it (valid == false contributes zeros).
+// group (lane r takes slots r, r + L, ...: coalesced) and combined across
+// the group by force_sums, in a fixed order: every lane of the group ends
+// with the totals. One memory round trip instead of s dependent ones. All
+// lanes of the wave must call it (valid == false contributes zeros).
 __device__ __forceinline__ void reduce_slices(const double* __restrict__ part, int s, long long cs,
                                               int k, int L, int r, bool valid, double (&f)[6]) {
 #pragma unroll
@@ -523,7 +604,7 @@ __device__ __forceinline__ void reduce_slices(const double* __restrict__ part, i
       for (int q = 0; q < 6; ++q) f[q] += o[q * cs + sl];
     }
   }
-  group_sum(f, L);
+  force_sums(f, L);
 }
 
 // Workgroup-local bookkeeping, flushed to the Sched record with one atomic
@@ -642,7 +723,7 @@ __device__ __forceinline__ void correct_body(const Dev& d, const Consts& c, int 
       // The sum reduce_slices forms from the same one slot per lane.
 #pragma unroll
       for (int q = 0; q < 6; ++q) f[q] = (valid && r < p.s) ? 0.0 + g1[q] : 0.0;
-      group_sum(f, L);
+      force_sums(f, L);
     } else {
       reduce_slices(d.part, p.s, c.part_cs, k, L, r, valid, f);
     }
