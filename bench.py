@@ -82,14 +82,14 @@ def force_traffic(workload):
         return None
 
 
-def cpu_baseline(w, seconds):
-    """The oracle on a bounded sample of the workload: its O(N^2) initial
-    force, then block steps from t = 0 until about `seconds` of wall time."""
+def _oracle_rate(w, seconds, threads):
+    """Pair interactions per second of the oracle over a bounded sample of the
+    workload: its O(N^2) initial force, then block steps from t = 0 until about
+    `seconds` of wall time (or t_end)."""
     import oracle
     from synth_inputs import plummer
 
     m, x, v = plummer(w["n"], w["seed"])
-    threads = oracle.max_threads()
     t0 = time.perf_counter()
     s = oracle.State(m, x, v, w["eps"], w["eta"], w["dt_max"], w["dt_min"], threads=threads)
     pairs = w["n"] * w["n"]
@@ -99,13 +99,41 @@ def cpu_baseline(w, seconds):
         pairs += len(act) * w["n"]
         nsteps += 1
     el = time.perf_counter() - t0
+    sample = (f"initial O(N^2) force + first {nsteps} block steps (to t={s.t_now:.6g}) of the "
+              f"same workload; {pairs:.3e} pairs in {el:.1f} s")
+    return pairs / el, sample
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(w, seconds):
+    """The oracle as it stands, on all the threads it is given (OpenMP over i)
+    and on one thread (a third of the sample time), with the host's CPU model
+    and CPU counts."""
+    import oracle
+
+    threads = oracle.max_threads()
+    value, sample = _oracle_rate(w, seconds, threads)
+    v1, sample1 = _oracle_rate(w, seconds / 3.0, 1)
     return {
-        "value": pairs / el,
+        "value": value,
         "unit": "pair-interactions/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": (f"initial O(N^2) force + first {nsteps} block steps (to t={s.t_now:.6g}) of the "
-                   f"same workload; {pairs:.3e} pairs in {el:.1f} s"),
+        "sample": sample,
+        "single_thread": {"value": v1, "sample": sample1},
+        "cpu_model": _cpu_model(),
+        "host_cpus": os.cpu_count(),
+        "usable_cpus": len(os.sched_getaffinity(0)),
     }
 
 

@@ -31,3 +31,14 @@ def test_traffic_read_only_for_unchanged_kernel(tmp_path, monkeypatch):
 def test_traffic_missing_summary(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(tmp_path / "absent.md"))
     assert bench.force_traffic("plummer_n16384") is None
+
+
+def test_cpu_baseline_fields():
+    """The oracle leg on a tiny workload: both rates positive, the thread
+    count and the host description reported."""
+    w = {"n": 64, "seed": 1, "eps": 1e-4, "eta": 0.01, "dt_max": 0.125, "dt_min": 2.0 ** -22, "t_end": 0.125}
+    cb = bench.cpu_baseline(w, 0.3)
+    assert cb["kind"] == "oracle" and cb["unit"] == "pair-interactions/s"
+    assert cb["value"] > 0 and cb["single_thread"]["value"] > 0
+    assert cb["cores"] >= 1 and cb["usable_cpus"] >= 1
+    assert "block steps" in cb["sample"] and "block steps" in cb["single_thread"]["sample"]
