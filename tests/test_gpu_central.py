@@ -82,3 +82,53 @@ def test_run_against_oracle(system):
     assert st["e"] == pytest.approx(rows[-1, 3], rel=1e-10)
     assert np.abs(host(cl.state()[0]) - ref.x).max() < 1e-9
     cl.close()
+
+
+@pytest.mark.parametrize("flags,tol", [(g.GD_FLAG_MIXED, 2e-6), (0, 1e-12)])
+def test_full_size_sampled(flags, tol):
+    """The full central-particle workload: 2^20 stars plus the central particle
+    (seed 7, dt_min 2^-22), in mixed precision (its configuration) and FP64.
+    Initial forces of 1024 random stars, the central particle and its 64
+    nearest stars against the oracle's compensated sums (mixed: 2e-6, FP64:
+    1e-12 per particle); then 3 block steps from the GPU's state with the
+    active set and times identical to the oracle's step, and the new block
+    steps too (FP64; in mixed precision a particle whose Aarseth step lies
+    within the mixed error of a power of two may take the neighbouring level:
+    at most one such tie per step, a factor of exactly 2)."""
+    ns = 1 << 20
+    m, x, v = plummer_with_bh(ns, 7)
+    cl = g.Cluster(m, x, v, eta=ETA, eps=EPS, dt_max=DTMAX, dt_min=DTMIN, device=DEV, eps_bh=EPS_BH,
+                   bh_index=ns, flags=flags)
+    r = np.linalg.norm(x[:ns], axis=1)
+    idx = np.unique(np.concatenate([np.random.default_rng(11).choice(ns, 1024, replace=False),
+                                    np.argsort(r)[:64], [ns]]))
+    _, _, a, j, _, _, _ = cl.state()
+    ra, rj = oracle.force(m, x, v, EPS, idx=idx, compensated=True, threads=oracle.max_threads(),
+                          eps_bh=EPS_BH, bh=ns)
+    ea, ej = rel_err_rows(host(a)[idx], ra), rel_err_rows(host(j)[idx], rj)
+    print(f"flags={flags}: max rel err acc {ea.max():.2e} jerk {ej.max():.2e}; central particle "
+          f"acc {ea[-1]:.2e} jerk {ej[-1]:.2e}")
+    assert ea.max() <= tol and ej.max() <= tol
+    idx_t = torch.empty(ns + 1, dtype=torch.int32, device=DEV)
+    for step in range(3):
+        xs, vs, a, j, t_i, dt_i, t_now = cl.state()
+        ref = oracle.State.from_arrays(m, host(xs), host(vs), host(a), host(j), host(t_i), host(dt_i), t_now,
+                                       EPS, ETA, DTMAX, DTMIN, threads=oracle.max_threads(), eps_bh=EPS_BH, bh=ns)
+        act_ref = ref.block_step()
+        g.gd_predict(cl.ctx)
+        n_act = g.gd_active(cl.ctx, idx_t)
+        np.testing.assert_array_equal(np.sort(host(idx_t[:n_act])), act_ref)
+        g.gd_force(cl.ctx)
+        g.gd_correct(cl.ctx)
+        _, _, _, _, t_i, dt_i, t_now = cl.state()
+        assert t_now == ref.t_now
+        np.testing.assert_array_equal(host(t_i), ref.t_i)
+        dt_gpu = host(dt_i)
+        if flags == 0:
+            np.testing.assert_array_equal(dt_gpu, ref.dt_i)
+        else:
+            diff = np.nonzero(dt_gpu != ref.dt_i)[0]
+            assert len(diff) <= 1
+            for i in diff:
+                assert dt_gpu[i] in (2.0 * ref.dt_i[i], 0.5 * ref.dt_i[i])
+    cl.close()

@@ -3,12 +3,14 @@ eta 0.01, dt_max 1/8), in the launch configuration the benchmark times
 (gd_init / gd_reinit, then gd_step_to replaying captured block steps).
 
 The oracle computes sampled outputs one by one: forces of 1024 sampled
-particles after the initial evaluation, and the whole integration to
+particles after the initial evaluation, one block step in each block-size
+bucket taken from the GPU's own state, and the whole integration to
 t = 1/8 (3411 block steps, about 1.4e10 pair interactions on the host's
 cores), compared on step counts, energy and final state.
 """
 import numpy as np
 import pytest
+import torch
 
 import oracle
 from paper_1702_00440_amd import gravidy as g
@@ -65,4 +67,47 @@ def test_run_to_one_eighth_against_oracle(ics):
     # 3411 steps of a chaotic system: rounding differences grow, but stay small
     assert np.abs(host(xs) - ref.x).max() < 1e-9
     assert np.abs(host(vs) - ref.v).max() < 1e-8
+    cl.close()
+
+
+def test_block_steps_in_every_size_bucket(ics):
+    """Block steps of the benchmark workload, stepped one at a time from t = 0:
+    the first step whose N_act falls in each bucket (1, 2-7, 8-63, 64-1023,
+    1024-16384) is replayed by the oracle from the GPU's state before it.
+    Active set, times and levels must be identical; positions and velocities
+    within 1e-13, acceleration and jerk within 1e-12 (relative, per particle)."""
+    m, x, v = ics
+    n = W["n"]
+    cl = _cluster(m, x, v)
+    buckets = [(1, 1), (2, 7), (8, 63), (64, 1023), (1024, n)]
+    seen = {}
+    idx = torch.empty(n, dtype=torch.int32, device=DEV)
+    steps = 0
+    while len(seen) < len(buckets):
+        pre = cl.state()
+        assert pre[6] <= 0.25, f"buckets not all reached by t = 1/4: {sorted(seen)}"
+        g.gd_predict(cl.ctx)
+        n_act = g.gd_active(cl.ctx, idx)
+        b = next(k for k, (lo, hi) in enumerate(buckets) if lo <= n_act <= hi)
+        act_gpu = np.sort(host(idx[:n_act])) if b not in seen else None
+        g.gd_force(cl.ctx)
+        g.gd_correct(cl.ctx)
+        steps += 1
+        if b in seen:
+            continue
+        seen[b] = n_act
+        xs, vs, a, j, t_i, dt_i, t_now = pre
+        ref = oracle.State.from_arrays(m, host(xs), host(vs), host(a), host(j), host(t_i), host(dt_i), t_now,
+                                       W["eps"], W["eta"], W["dt_max"], W["dt_min"], threads=oracle.max_threads())
+        act_ref = ref.block_step()
+        np.testing.assert_array_equal(act_gpu, act_ref)
+        xs, vs, a, j, t_i, dt_i, t_now = cl.state()
+        assert t_now == ref.t_now
+        np.testing.assert_array_equal(host(t_i), ref.t_i)
+        np.testing.assert_array_equal(host(dt_i), ref.dt_i)
+        assert rel_err_rows(host(xs), ref.x).max() <= 1e-13
+        assert rel_err_rows(host(vs), ref.v).max() <= 1e-13
+        assert rel_err_rows(host(a)[act_ref], ref.a[act_ref]).max() <= 1e-12
+        assert rel_err_rows(host(j)[act_ref], ref.jk[act_ref]).max() <= 1e-12
+    print(f"{steps} steps; N_act per bucket: {[seen[k] for k in range(len(buckets))]}")
     cl.close()
