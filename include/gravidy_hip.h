@@ -129,6 +129,7 @@ gd_status gd_reinit(gd_ctx* c, const double* m, const double* x, const double* v
  * call. gd_profile_get reports the summed milliseconds, the number of such
  * launches, and their pair interactions (N_act * N each). Host outputs; any
  * may be NULL. Results are identical with and without timing.
+ * Errors: GD_EINVAL for a NULL context; GD_EHIP (event creation).
  */
 gd_status gd_profile_force(gd_ctx* c, int enable);
 gd_status gd_profile_get(gd_ctx* c, double* force_ms, int64_t* launches, int64_t* pairs);
@@ -141,6 +142,7 @@ gd_status gd_profile_get(gd_ctx* c, double* force_ms, int64_t* launches, int64_t
  * edges (1, 2, 8, 64, 1024, 4096), the summed milliseconds, the number of
  * launches and their pair interactions. Counters restart with
  * gd_profile_force.
+ * Errors: GD_EINVAL for a NULL context.
  */
 #define GD_PROFILE_BUCKETS 6
 gd_status gd_profile_buckets(gd_ctx* c, int64_t* n_act_min, double* force_ms, int64_t* launches,
@@ -318,7 +320,7 @@ const char* gd_pool_last_error(const gd_pool* pool);
 gd_status gd_stats_get(gd_ctx* c, gd_stats* st);
 
 /*
- * Histogram of the active-block sizes (the block steps of Sec. 2.2): counts[b]
+ * Histogram of the active-block sizes (the block time steps of Sec. 2.4): counts[b]
  * (host, GD_NACT_BINS entries) receives the number of block steps taken with
  * 2^b <= N_act < 2^(b+1) since gd_init, gd_reinit or gd_set_state. The counts
  * sum to gd_stats.block_steps. Synchronises.

@@ -363,9 +363,23 @@ gd_status gd_reinit(gd_ctx* c, const double* m, const double* x, const double* v
 gd_status gd_profile_force(gd_ctx* c, int enable) {
   if (!c) return GD_EINVAL;
   if (enable && !c->ev_ready) {
-    for (int k = 0; k < kGraphSteps + 1; ++k) {
-      GD_TRY(c->hip(hipEventCreate(&c->ev_s[k]), "event create"));
-      GD_TRY(c->hip(hipEventCreate(&c->ev_e[k]), "event create"));
+    // All events or none: a partial set is destroyed again, so that a later
+    // call (or gd_destroy) never sees events it did not record as made.
+    int k = 0;
+    hipError_t e = hipSuccess;
+    for (; k < kGraphSteps + 1; ++k) {
+      if ((e = hipEventCreate(&c->ev_s[k])) != hipSuccess) break;
+      if ((e = hipEventCreate(&c->ev_e[k])) != hipSuccess) {
+        (void)hipEventDestroy(c->ev_s[k]);
+        break;
+      }
+    }
+    if (e != hipSuccess) {
+      for (int q = 0; q < k; ++q) {
+        (void)hipEventDestroy(c->ev_s[q]);
+        (void)hipEventDestroy(c->ev_e[q]);
+      }
+      return c->hip(e, "event create");
     }
     c->ev_ready = true;
   }
