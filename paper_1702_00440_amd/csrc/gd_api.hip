@@ -26,6 +26,7 @@ using namespace gd;
 namespace {
 
 constexpr int kGraphSteps = 64;  // block steps per captured graph
+constexpr int kSchedWords = (int)((sizeof(Sched) + 7) / 8);  // 8-byte words of a status copy
 // Force-timing buckets by N_act: lower edges (the last bucket is open).
 constexpr int kProfBuckets = GD_PROFILE_BUCKETS;
 constexpr long long kProfEdges[kProfBuckets] = {1, 2, 8, 64, 1024, 4096};
@@ -178,7 +179,13 @@ struct gd_ctx {
   Dev d{};
   hipStream_t stream = nullptr;
   hipStream_t capture_stream = nullptr;
-  hipGraphExec_t graph = nullptr;
+  // Two instances of the captured block steps, each ending with a copy of the
+  // schedule record into its own pinned buffer (h_ring[0] / h_ring[1]), with
+  // an event recorded after each launch: replays can then be queued ahead of
+  // the host reading an earlier replay's status.
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  Sched* h_ring[2] = {nullptr, nullptr};
+  hipEvent_t ev_ring[2] = {nullptr, nullptr};
   bool prof = false, ev_ready = false;
   hipEvent_t ev_s[kGraphSteps + 1] = {}, ev_e[kGraphSteps + 1] = {};
   double prof_ms = 0.0;
@@ -243,7 +250,21 @@ gd_status enqueue_step(gd_ctx* c, hipStream_t s, hipEvent_t ev_s, hipEvent_t ev_
 }
 
 // Captures kGraphSteps block steps into *out.
-gd_status build_graph(gd_ctx* c, hipGraphExec_t* out) {
+}  // namespace
+
+// The schedule record copied, word by word, to pinned host memory: the last
+// node of a replayed graph, so that the host reads a replay's status without
+// a separate copy. The source may be read up to 7 bytes past the record,
+// inside the workspace (the next array starts 256 bytes later at the least).
+__global__ void k_status_out(const unsigned long long* __restrict__ sc, unsigned long long* __restrict__ out) {
+  for (int k = threadIdx.x; k < kSchedWords; k += blockDim.x) out[k] = sc[k];
+  __threadfence_system();
+}
+
+namespace {
+
+gd_status build_graph(gd_ctx* c, int ring) {
+  hipGraphExec_t* out = &c->graph[ring];
   if (*out) return GD_OK;
   hipGraph_t g = nullptr;
   GD_TRY(c->hip(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal),
@@ -251,6 +272,11 @@ gd_status build_graph(gd_ctx* c, hipGraphExec_t* out) {
   gd_status st = GD_OK;
   for (int k = 0; k < kGraphSteps && st == GD_OK; ++k)
     st = enqueue_step(c, c->capture_stream, nullptr, nullptr);
+  if (st == GD_OK) {
+    hipLaunchKernelGGL(k_status_out, dim3(1), dim3(64), 0, c->capture_stream,
+                       (const unsigned long long*)c->d.sc, (unsigned long long*)c->h_ring[ring]);
+    st = c->hip(hipGetLastError(), "status kernel");
+  }
   hipError_t e = hipStreamEndCapture(c->capture_stream, &g);
   if (st != GD_OK) {
     if (g) (void)hipGraphDestroy(g);
@@ -347,6 +373,13 @@ gd_status gd_init(gd_ctx** out, const gd_params* p, int64_t n, const double* m, 
   if ((st = c->hip(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking),
                    "capture stream")) != GD_OK)
     return cleanup_fail(st);
+  for (int r = 0; r < 2; ++r) {
+    if ((st = c->hip(hipHostMalloc((void**)&c->h_ring[r], 8 * (size_t)kSchedWords, hipHostMallocDefault),
+                     "pinned status ring")) != GD_OK)
+      return cleanup_fail(st);
+    if ((st = c->hip(hipEventCreateWithFlags(&c->ev_ring[r], hipEventDisableTiming), "status event")) != GD_OK)
+      return cleanup_fail(st);
+  }
 
   c->d_eres = d.ebuf + 3 * (size_t)make_eplan((int)n).items;
   if ((st = initialise(c, m, x, v)) != GD_OK) return cleanup_fail(st);
@@ -483,6 +516,45 @@ gd_status gd_correct(gd_ctx* c) {
   return GD_OK;
 }
 
+namespace {
+
+// Graph replays until the schedule reaches chunk_end; on return h_sc holds
+// the status after the last replay that did work. The next replay is queued
+// before the host reads the previous one's status, so that the device does
+// not wait for the host between replays, unless the replay in flight is
+// likely to end the chunk (the time left is under twice what the last replay
+// covered). A replay queued after the stop time is reached does nothing: the
+// device skips every step past it.
+gd_status replay_chunk(gd_ctx* c, long long chunk_end) {
+  int next = 0, head = 0, inflight = 0;
+  long long t_prev = c->t_now, adv = 0;
+  auto queue = [&]() -> gd_status {
+    GD_TRY(c->hip(hipGraphLaunch(c->graph[next], c->stream), "graph launch"));
+    GD_TRY(c->hip(hipEventRecord(c->ev_ring[next], c->stream), "status event"));
+    next ^= 1;
+    ++inflight;
+    return GD_OK;
+  };
+  GD_TRY(queue());
+  for (;;) {
+    if (inflight == 1 && adv > 0 && chunk_end - t_prev > 2 * adv) GD_TRY(queue());
+    GD_TRY(c->hip(hipEventSynchronize(c->ev_ring[head]), "status wait"));
+    *c->h_sc = *c->h_ring[head];
+    head ^= 1;
+    --inflight;
+    if (c->h_sc->nonfinite) {
+      (void)hipStreamSynchronize(c->stream);
+      return c->fail(GD_ENONFINITE, "non-finite acceleration or jerk");
+    }
+    adv = c->h_sc->t_now - t_prev;
+    t_prev = c->h_sc->t_now;
+    if (c->h_sc->t_now >= chunk_end) return GD_OK;
+    if (inflight == 0) GD_TRY(queue());
+  }
+}
+
+}  // namespace
+
 gd_status gd_step_to(gd_ctx* c, double t_end, gd_stats* st) {
   if (!c) return GD_EINVAL;
   if (c->phase == kPredictedAuto || c->phase == kForcedAuto)
@@ -500,7 +572,10 @@ gd_status gd_step_to(gd_ctx* c, double t_end, gd_stats* st) {
   if (target < c->t_now) return c->fail(GD_EINVAL, "t_end is before the current time");
   // Profiling runs the same steps as direct launches (the force launches
   // carry timing events); otherwise a captured graph is replayed.
-  if (!c->prof) GD_TRY(build_graph(c, &c->graph));
+  if (!c->prof) {
+    GD_TRY(build_graph(c, 0));
+    GD_TRY(build_graph(c, 1));
+  }
   c->phase = kIdle;
   GD_TRY(read_sched(c));
   long long steps_before = c->h_sc->block_steps, pairs_before = c->h_sc->pairs;
@@ -508,35 +583,39 @@ gd_status gd_step_to(gd_ctx* c, double t_end, gd_stats* st) {
     // Advance to the next multiple of dt_max, where all particles meet.
     const long long chunk_end = (c->t_now / per_max + 1) * per_max;
     GD_TRY(c->hip(launch_set_tend(c->d, chunk_end, c->stream), "prepare"));
+    if (!c->prof) {
+      GD_TRY(replay_chunk(c, chunk_end));
+      c->t_now = c->h_sc->t_now;
+      double e[3];
+      GD_TRY(energy_now(c, 0, e));
+      c->e_last = e[0] + e[1];
+      continue;
+    }
+    // Timing: the same steps as direct launches, 64 at a time, each force
+    // launch between its own events and each step's N_act logged.
     for (;;) {
-      if (c->prof) {
-        for (int k = 0; k < kGraphSteps; ++k) {
-          GD_TRY(enqueue_step(c, c->stream, c->ev_s[k], c->ev_e[k]));
-          GD_TRY(c->hip(launch_log_nact(c->d, c->d.nact_log + k, c->stream), "log kernel"));
-        }
-        GD_TRY(c->hip(hipMemcpyAsync(c->h_nact, c->d.nact_log, sizeof(int) * kGraphSteps,
-                                     hipMemcpyDeviceToHost, c->stream),
-                      "read log"));
-      } else {
-        GD_TRY(c->hip(hipGraphLaunch(c->graph, c->stream), "graph launch"));
+      for (int k = 0; k < kGraphSteps; ++k) {
+        GD_TRY(enqueue_step(c, c->stream, c->ev_s[k], c->ev_e[k]));
+        GD_TRY(c->hip(launch_log_nact(c->d, c->d.nact_log + k, c->stream), "log kernel"));
       }
+      GD_TRY(c->hip(hipMemcpyAsync(c->h_nact, c->d.nact_log, sizeof(int) * kGraphSteps,
+                                   hipMemcpyDeviceToHost, c->stream),
+                    "read log"));
       GD_TRY(read_sched(c));
       if (c->h_sc->nonfinite) return c->fail(GD_ENONFINITE, "non-finite acceleration or jerk");
-      if (c->prof) {
-        // Steps run in order; the first (block_steps delta) of the replay were real.
-        const long long ran = c->h_sc->block_steps - steps_before;
-        for (long long k = 0; k < ran && k < kGraphSteps; ++k) {
-          float ms = 0.f;
-          GD_TRY(c->hip(hipEventElapsedTime(&ms, c->ev_s[k], c->ev_e[k]), "event time"));
-          c->prof_ms += ms;
-          const int b = prof_bucket(c->h_nact[k]);
-          c->bucket_ms[b] += ms;
-          c->bucket_launches[b] += 1;
-          c->bucket_pairs[b] += (long long)c->h_nact[k] * c->n;
-        }
-        c->prof_launches += ran;
-        c->prof_pairs += c->h_sc->pairs - pairs_before;
+      // Steps run in order; the first (block_steps delta) of the batch were real.
+      const long long ran = c->h_sc->block_steps - steps_before;
+      for (long long k = 0; k < ran && k < kGraphSteps; ++k) {
+        float ms = 0.f;
+        GD_TRY(c->hip(hipEventElapsedTime(&ms, c->ev_s[k], c->ev_e[k]), "event time"));
+        c->prof_ms += ms;
+        const int b = prof_bucket(c->h_nact[k]);
+        c->bucket_ms[b] += ms;
+        c->bucket_launches[b] += 1;
+        c->bucket_pairs[b] += (long long)c->h_nact[k] * c->n;
       }
+      c->prof_launches += ran;
+      c->prof_pairs += c->h_sc->pairs - pairs_before;
       steps_before = c->h_sc->block_steps;
       pairs_before = c->h_sc->pairs;
       if (c->h_sc->t_now >= chunk_end) break;
@@ -647,7 +726,11 @@ gd_status gd_stats_get(gd_ctx* c, gd_stats* st) {
 
 void gd_destroy(gd_ctx* c) {
   if (!c) return;
-  if (c->graph) (void)hipGraphExecDestroy(c->graph);
+  for (int r = 0; r < 2; ++r) {
+    if (c->graph[r]) (void)hipGraphExecDestroy(c->graph[r]);
+    if (c->ev_ring[r]) (void)hipEventDestroy(c->ev_ring[r]);
+    if (c->h_ring[r]) (void)hipHostFree(c->h_ring[r]);
+  }
   if (c->ev_ready)
     for (int k = 0; k < kGraphSteps + 1; ++k) {
       (void)hipEventDestroy(c->ev_s[k]);
