@@ -224,15 +224,22 @@ def main():
     pairs = 0
     drift = 0.0
     stats = None
-    for _ in range(args.steps):
+    marks = [ev0]
+    for k in range(args.steps):
         stats, d = one_step()
         pairs += stats["pair_interactions"] + n * n
         drift = max(drift, d)
+        if k + 1 < args.steps:
+            e = torch.cuda.Event(enable_timing=True)
+            e.record(stream)
+            marks.append(e)
     ev1.record(stream)
+    marks.append(ev1)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     gpu_ms = ev0.elapsed_time(ev1)
     elapsed = max(wall, gpu_ms / 1e3)
+    step_ms = [marks[k].elapsed_time(marks[k + 1]) for k in range(len(marks) - 1)]
     hist = nact_histogram(g.gd_nact_histogram(ctx))
     prof = {"force_ms": 0.0, "launches": 0, "pairs": 0}
     buckets = []
@@ -265,6 +272,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": elapsed * 1e3 / args.steps,
+        "step_ms": step_ms,
+        "ms_per_step_median": sorted(step_ms)[len(step_ms) // 2],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

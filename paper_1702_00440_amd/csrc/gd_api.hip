@@ -254,8 +254,8 @@ gd_status enqueue_step(gd_ctx* c, hipStream_t s, hipEvent_t ev_s, hipEvent_t ev_
 
 // The schedule record copied, word by word, to pinned host memory: the last
 // node of a replayed graph, so that the host reads a replay's status without
-// a separate copy. The source may be read up to 7 bytes past the record,
-// inside the workspace (the next array starts 256 bytes later at the least).
+// a separate copy.
+static_assert(sizeof(Sched) % 8 == 0, "the status copy moves whole 8-byte words");
 __global__ void k_status_out(const unsigned long long* __restrict__ sc, unsigned long long* __restrict__ out) {
   for (int k = threadIdx.x; k < kSchedWords; k += blockDim.x) out[k] = sc[k];
   __threadfence_system();

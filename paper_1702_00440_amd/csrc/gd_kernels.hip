@@ -337,10 +337,11 @@ __device__ __forceinline__ Plan make_plan_wave(int n_act, int n, int lane) {
 //     several pair evaluations;
 //   - j particles of the slice go through LDS in tiles of kTileJ, loaded
 //     with coalesced SoA reads and prefetched into registers one tile ahead;
-//   - the LJ lanes of one i are reduced with a fixed xor butterfly, and each
-//     slice writes its partial sum to part[component][position][slot], so
-//     that the slices of one particle are contiguous for the reduction
-//     (slice_slot keeps the slices that one XCD computes next to each other).
+//   - the LJ lanes of one i pair reduce their sums by halving (quarter_sums)
+//     inside the wave, and each slice writes its partial sum to
+//     part[component][position][slot], so that the slices of one particle
+//     are contiguous for the reduction (slice_slot keeps the slices that one
+//     XCD computes next to each other).
 // The slices of a particle are summed afterwards by the kernel that consumes
 // the force (corrector, initial steps, or output), in an order that depends
 // only on (n_act, n).
