@@ -149,7 +149,9 @@ const char* check_params(const gd_params* p, int64_t n, int* kmax_out) {
   return nullptr;
 }
 
-Consts make_consts(const gd_params* p, int64_t n, int kmax) {
+// Constants of a context (pool == false) or of a pool's cluster (pool ==
+// true: pools run the force kernel with kIPerLane i per lane).
+Consts make_consts(const gd_params* p, int64_t n, int kmax, bool pool) {
   Consts c{};
   c.n = (int)n;
   c.kmax = kmax;
@@ -161,9 +163,10 @@ Consts make_consts(const gd_params* p, int64_t n, int kmax) {
   c.eps2 = p->eps * p->eps;
   c.bh = (int)p->bh_index;
   c.eps2_bh = p->bh_index >= 0 ? p->eps_bh * p->eps_bh : c.eps2;
-  launch_grids((int)n, &c.force_grid, &c.correct_grid);
+  c.ipl = (!pool && n >= kLargeN && p->eps > 0.0) ? kIPerLaneLarge : kIPerLane;
+  launch_grids((int)n, c.ipl, &c.force_grid, &c.correct_grid);
   c.mixed = (p->flags & GD_FLAG_MIXED) ? 1 : 0;
-  const Plan p1 = make_plan(1, (int)n);
+  const Plan p1 = make_plan(1, (int)n, c.ipl);
   c.lj1 = p1.lj;
   c.s1 = p1.s;
   c.part_cs = partial_rows(n);
@@ -353,7 +356,7 @@ gd_status gd_init(gd_ctx** out, const gd_params* p, int64_t n, const double* m, 
   if (!c) return bad(GD_EINVAL, "out of host memory");
   c->p = *p;
   c->n = n;
-  c->c = make_consts(p, n, kmax);
+  c->c = make_consts(p, n, kmax, false);
   c->stream = (hipStream_t)hip_stream;
   c->d = carve(workspace, L);
   Dev& d = c->d;
@@ -979,7 +982,7 @@ gd_status gd_pool_admit(gd_pool* P, int64_t n, const double* m, const double* x,
   s.bytes = L.total;
   s.t_end = (long long)q * (1LL << kmax);
   s.d = carve(P->arena + off, L);
-  s.c = make_consts(&P->p, n, kmax);
+  s.c = make_consts(&P->p, n, kmax, true);
   // Initialisation of the cluster (Sec. 2.4 steps 2-3) on the pool stream.
   auto undo = [&](gd_status st) {
     s = PoolSlotHost();

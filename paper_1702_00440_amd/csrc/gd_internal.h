@@ -11,8 +11,14 @@ namespace gd {
 constexpr int kBlock = 256;
 // j particles staged per LDS tile.
 constexpr int kTileJ = 256;
-// i particles held per lane by the force kernel.
+// i particles held per lane by the force kernel: kIPerLane, or
+// kIPerLaneLarge in contexts of at least kLargeN particles with eps > 0. More
+// i per lane give each lane more independent pair chains and each LDS read
+// of j more pairs, which long items repay; at smaller N the mid-size blocks
+// are faster with 2 (and pools always use 2).
 constexpr int kIPerLane = 2;
+constexpr int kIPerLaneLarge = 4;
+constexpr int kLargeN = 131072;
 // Work items the force decomposition aims for (about 4 workgroups per CU).
 constexpr int kTargetItems = 1024;
 // Upper bound of the force grid: workgroups loop over items beyond it.
@@ -26,7 +32,7 @@ constexpr int kMinJPerLane = 4;
 // chain of pair evaluations with more lanes per i instead (LJ up to 64).
 constexpr int kMinSlice = kTileJ;
 // Smallest log2 of the lanes that share one i: i tiles hold at most
-// (kBlock >> kMinLj) * kIPerLane = 32 particles, which keeps the number of
+// (kBlock >> kMinLj) * ipl = 32 (or 64) particles, which keeps the number of
 // j slices (and so the partial sums to reduce) small for large blocks.
 constexpr int kMinLj = 4;
 // Energy: fixed grid of slice items.
@@ -46,7 +52,7 @@ enum : int { kPredAuto = 0, kPredAll = 1, kPredExplicit = 2 };
 
 // Decomposition of one force launch over (i tile, j slice) items.
 //   lj   : log2 of the lanes sharing one i (LJ = 1 << lj, 1..64, in one wave)
-//   it   : i particles per workgroup tile = (kBlock >> lj) * kIPerLane
+//   it   : i particles per workgroup tile = (kBlock >> lj) * ipl
 //   nit  : number of i tiles
 //   s    : number of j slices; item = itile * s + slice
 //   len  : j particles per slice
@@ -74,12 +80,12 @@ struct Sched {
 // The plan depends only on (n_act, n). The kernel that fixes n_act for a
 // step (predictor, or the explicit index list) stores it in the Sched record,
 // and the force kernel and every slice reduction read that one copy.
-// The decomposition with LJ = 2^lj lanes per i; *stop tells whether make_plan
-// takes it (enough items, or the last candidate).
-__host__ __device__ inline Plan plan_for_lj(int n_act, int n, int lj, bool* stop) {
+// The decomposition with LJ = 2^lj lanes per i and ipl i per lane; *stop
+// tells whether make_plan takes it (enough items, or the last candidate).
+__host__ __device__ inline Plan plan_for_lj(int n_act, int n, int lj, int ipl, bool* stop) {
   int max_s = (n + kMinSlice - 1) / kMinSlice;
   if (max_s < 1) max_s = 1;
-  const int it = (kBlock >> lj) * kIPerLane;
+  const int it = (kBlock >> lj) * ipl;
   int nit = (n_act + it - 1) / it;
   if (nit < 1) nit = 1;
   int s = kTargetItems / nit;
@@ -101,19 +107,20 @@ __host__ __device__ inline Plan plan_for_lj(int n_act, int n, int lj, bool* stop
 }
 
 // The first lj from kMinLj up that gives enough items (or the last one).
-__host__ __device__ inline Plan make_plan(int n_act, int n) {
+__host__ __device__ inline Plan make_plan(int n_act, int n, int ipl) {
   for (int lj = kMinLj;; ++lj) {
     bool stop = false;
-    const Plan p = plan_for_lj(n_act, n, lj, &stop);
+    const Plan p = plan_for_lj(n_act, n, lj, ipl, &stop);
     if (stop) return p;
   }
 }
 
 // Rows of the partial-force buffer a context of n particles needs: for every
 // plan, s * n_act <= s * nit * it <= max(nit, kTargetItems) * it with
-// it <= 32, and s * n_act <= (n / kMinSlice rounded up) * n.
+// it <= 64 (either i count per lane), and s * n_act <= (n / kMinSlice
+// rounded up) * n. The size does not depend on the i count per lane.
 inline long long partial_rows(long long n) {
-  const long long it_max = (long long)(kBlock >> kMinLj) * kIPerLane;
+  const long long it_max = (long long)(kBlock >> kMinLj) * kIPerLaneLarge;
   const long long by_items = n + it_max + (long long)kTargetItems * it_max;
   const long long by_slices = ((n + kMinSlice - 1) / kMinSlice) * n;
   const long long rows = by_items < by_slices ? by_items : by_slices;
@@ -166,6 +173,7 @@ struct Consts {
   int mixed;         // 1: pair arithmetic in mixed precision (GD_FLAG_MIXED)
   double dt_min, dt_max, eta, eps2, eps2_bh;
   double inv_dt_min, inv_dt_max;  // exact reciprocals (powers of two)
+  int ipl;            // i particles per lane of the force kernel (kIPerLane or kIPerLaneLarge)
   int lj1, s1;        // decomposition of a one-particle block: log2 lanes per i, j slices
   long long part_cs;  // component stride of the partial-force buffer (partial_rows(n))
 };
@@ -181,12 +189,12 @@ __host__ __device__ inline int correct_lanes(int s) {
 // Launch sizes for a context of n particles: enough workgroups for the
 // largest force decomposition and corrector layout over all block sizes
 // (sampled), capped; kernels loop over anything beyond the grid.
-inline void launch_grids(int n, int* force_grid, int* correct_grid) {
+inline void launch_grids(int n, int ipl, int* force_grid, int* correct_grid) {
   long long fmax = 1, cmax = 1;
   const int step = n > 8192 ? n / 8192 : 1;
   for (int a = 1;; a += step) {
     if (a > n) a = n;
-    const Plan p = make_plan(a, n);
+    const Plan p = make_plan(a, n, ipl);
     if (p.items > fmax) fmax = p.items;
     const long long lanes = (long long)a * correct_lanes(p.s);
     const long long wg = (lanes + kBlock - 1) / kBlock;

@@ -304,12 +304,12 @@ __device__ __forceinline__ NextStep next_step_wave(int h, int lane, int kmax, lo
 
 // make_plan evaluated by one whole wave: lane l tries lj = kMinLj + l with
 // the same plan_for_lj, and the first lane that stops wins (its plan read
-// back lane by lane), so every lane returns make_plan(n_act, n).
-__device__ __forceinline__ Plan make_plan_wave(int n_act, int n, int lane) {
+// back lane by lane), so every lane returns make_plan(n_act, n, ipl).
+__device__ __forceinline__ Plan make_plan_wave(int n_act, int n, int ipl, int lane) {
   const int lj = kMinLj + lane;
   bool stop = false;
   Plan p{};
-  if (lj <= 6) p = plan_for_lj(n_act, n, lj, &stop);
+  if (lj <= 6) p = plan_for_lj(n_act, n, lj, ipl, &stop);
   const unsigned long long st = __ballot(stop);
   const int first = __ffsll((long long)st) - 1;
   Plan q;
@@ -333,7 +333,7 @@ __device__ __forceinline__ Plan make_plan_wave(int n_act, int n, int lane) {
 //   - inside a workgroup, LJ = 2^lj consecutive lanes share the same i
 //     particles and split the slice's j between them (LJ = 16 for most block
 //     sizes, up to 64 inside one wave);
-//   - each lane holds kIPerLane i particles, so one LDS read of j feeds
+//   - each lane holds kI i particles (2, or 4 in large contexts), so one LDS read of j feeds
 //     several pair evaluations;
 //   - j particles of the slice go through LDS in tiles of kTileJ, loaded
 //     with coalesced SoA reads and prefetched into registers one tile ahead;
@@ -346,32 +346,33 @@ __device__ __forceinline__ Plan make_plan_wave(int n_act, int n, int lane) {
 // the force (corrector, initial steps, or output), in an order that depends
 // only on (n_act, n).
 // i particles of one lane: predicted state, index, softening, accumulators.
+template <int kI>
 struct ILane {
-  double x[kIPerLane], y[kIPerLane], z[kIPerLane];
-  double vx[kIPerLane], vy[kIPerLane], vz[kIPerLane], e2[kIPerLane];
-  int g[kIPerLane], pos[kIPerLane];
-  Acc6 A[kIPerLane];
-  Acc6f Af[kIPerLane];  // mixed precision: sums of the current tile
+  double x[kI], y[kI], z[kI];
+  double vx[kI], vy[kI], vz[kI], e2[kI];
+  int g[kI], pos[kI];
+  Acc6 A[kI];
+  Acc6f Af[kI];  // mixed precision: sums of the current tile
 };
 
 // Pairs of one LDS tile of cnt j (first index jt). Lane jsub of each group of
 // LJ lanes takes j = jsub, jsub + LJ, ...: a uniform trip count over whole
 // groups of LJ (scalar loop control, no per-lane exit masks), then at most
 // one partial group.
-template <bool kMaskSelf, bool kMixed>
+template <bool kMaskSelf, bool kMixed, int kI>
 __device__ __forceinline__ void tile_pairs(const double (*sj)[kTileJ], int cnt, int LJ, int jsub,
-                                           int jt, double eps2, ILane& I) {
+                                           int jt, double eps2, ILane<kI>& I) {
   const int full = cnt & ~(LJ - 1);
   if (kMixed) {
 #pragma unroll
-    for (int q = 0; q < kIPerLane; ++q) I.Af[q] = Acc6f{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int q = 0; q < kI; ++q) I.Af[q] = Acc6f{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   }
   auto pairs_with = [&](int k) {
     const double xj = sj[0][k], yj = sj[1][k], zj = sj[2][k];
     const double vxj = sj[3][k], vyj = sj[4][k], vzj = sj[5][k];
     const double mj = sj[6][k];
 #pragma unroll
-    for (int q = 0; q < kIPerLane; ++q) {
+    for (int q = 0; q < kI; ++q) {
       // eps = 0: the j = i term (r = 0) is excluded explicitly; with eps > 0
       // it is exactly zero (r = w = 0, finite q).
       const bool self = kMaskSelf && (jt + k) == I.g[q];
@@ -391,7 +392,7 @@ __device__ __forceinline__ void tile_pairs(const double (*sj)[kTileJ], int cnt, 
   if (kMixed) {
     // At most kTileJ / LJ terms per lane in FP32, then into FP64.
 #pragma unroll
-    for (int q = 0; q < kIPerLane; ++q) {
+    for (int q = 0; q < kI; ++q) {
       I.A[q].ax += (double)I.Af[q].ax;
       I.A[q].ay += (double)I.Af[q].ay;
       I.A[q].az += (double)I.Af[q].az;
@@ -426,41 +427,71 @@ __device__ __forceinline__ void quarter_sums(const double (&v)[12], double (&t)[
   if constexpr (kLJ / 8 >= 1) group_sum(t, kLJ / 4);
 }
 
-// Reduction over the LJ lanes that share an i (consecutive lanes), then the
-// slice partials by list position, stored by the first lane of each quarter
-// of the group. The central particle's pairs (softened with eps_bh, once per
-// i, on slice 0; bx.. its predicted state) are added to the first lane's
-// sums before the reduction.
-template <bool kCentral>
+// The 24 sums of a group of kLJ lanes that share four i, reduced the same
+// way: the first exchange keeps i 0-1 in the lower half of the group and
+// i 2-3 in the upper, the next keeps the first i of each pair in the lower
+// quarter of the half, the next the acceleration in the lower eighth of the
+// quarter, and a butterfly sums the remaining 3 values over the eighth.
+template <int kLJ>
+__device__ __forceinline__ void eighth_sums(const double (&v)[24], double (&t)[3]) {
+  double h[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) h[k] = split_add<kLJ / 2>(v[k], v[12 + k]);
+  double u[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) u[k] = split_add<kLJ / 4>(h[k], h[6 + k]);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) t[k] = split_add<kLJ / 8>(u[k], u[3 + k]);
+  if constexpr (kLJ / 16 >= 1) group_sum(t, kLJ / 8);
+}
+
+// Reduction over the LJ lanes that share the lane's kI i (consecutive lanes),
+// then the slice partials by list position: each 3-vector (one i's
+// acceleration or jerk) is stored by the first lane of the part of the group
+// that holds it (LJ / (2 kI) lanes). The central particle's pairs (softened
+// with eps_bh, once per i, on slice 0; bx.. its predicted state) are added to
+// the first lane's sums before the reduction.
+template <bool kCentral, int kI>
 __device__ __forceinline__ void finish_item(const Dev& d, const Consts& c, int LJ, int jsub,
-                                            int slice, int s, int n_act, ILane& I, double bx,
+                                            int slice, int s, int n_act, ILane<kI>& I, double bx,
                                             double by, double bz, double bvx, double bvy,
                                             double bvz) {
-  static_assert(kIPerLane == 2, "the reduction splits the sums of two i");
+  static_assert(kI == 2 || kI == 4, "the reduction splits the sums of two or four i");
   if (kCentral && slice == 0 && jsub == 0) {
     const int b = c.bh;
     const double bm = d.m[b];
 #pragma unroll
-    for (int q = 0; q < kIPerLane; ++q)
+    for (int q = 0; q < kI; ++q)
       if (I.g[q] != b)
         pair_fp64(I.x[q], I.y[q], I.z[q], I.vx[q], I.vy[q], I.vz[q], bx, by, bz, bvx, bvy, bvz, bm,
                   c.eps2_bh, I.A[q]);
   }
-  double v[12];
+  double v[6 * kI];
 #pragma unroll
-  for (int q = 0; q < kIPerLane; ++q) {
+  for (int q = 0; q < kI; ++q) {
     v[6 * q + 0] = I.A[q].ax; v[6 * q + 1] = I.A[q].ay; v[6 * q + 2] = I.A[q].az;
     v[6 * q + 3] = I.A[q].jx; v[6 * q + 4] = I.A[q].jy; v[6 * q + 5] = I.A[q].jz;
   }
   double t[3];
-  if (LJ == 64) quarter_sums<64>(v, t);
-  else if (LJ == 32) quarter_sums<32>(v, t);
-  else quarter_sums<16>(v, t);
-  const int quarter = LJ >> 2;
-  if ((jsub & (quarter - 1)) == 0) {
-    const int q = jsub >= 2 * quarter;           // which i
-    const int comp = (jsub & quarter) ? 3 : 0;  // acceleration or jerk
-    const int pos = q ? I.pos[1] : I.pos[0];
+  if constexpr (kI == 2) {
+    if (LJ == 64) quarter_sums<64>(v, t);
+    else if (LJ == 32) quarter_sums<32>(v, t);
+    else quarter_sums<16>(v, t);
+  } else {
+    if (LJ == 64) eighth_sums<64>(v, t);
+    else if (LJ == 32) eighth_sums<32>(v, t);
+    else eighth_sums<16>(v, t);
+  }
+  const int part = LJ / (2 * kI);  // lanes that end with one 3-vector
+  if ((jsub & (part - 1)) == 0) {
+    // which i: the half, then (four i) the quarter; acceleration or jerk: the
+    // lower or upper part within that
+    const int q = kI == 2 ? (jsub >= LJ / 2) : 2 * (jsub >= LJ / 2) + ((jsub & (LJ / 4)) != 0);
+    const int comp = (jsub & part) ? 3 : 0;
+    // (explicit selects: an indexed read would keep the lane's i in memory)
+    int pos;
+    if constexpr (kI == 2) pos = q ? I.pos[1] : I.pos[0];
+    else pos = q == 0 ? I.pos[0] : q == 1 ? I.pos[1] : q == 2 ? I.pos[2] : I.pos[3];
     if (pos < n_act) {
       // part[component][position][slot], components part_cs apart
       const size_t cs = (size_t)c.part_cs;
@@ -472,7 +503,7 @@ __device__ __forceinline__ void finish_item(const Dev& d, const Consts& c, int L
   }
 }
 
-template <bool kMaskSelf, bool kCentral, bool kMixed>
+template <bool kMaskSelf, bool kCentral, bool kMixed, int kI>
 __device__ __forceinline__ void force_body(const Dev& d, const Consts& c, int blk, int nblk) {
   const Sched* __restrict__ sc = d.sc;
   const int n = c.n;
@@ -493,10 +524,10 @@ __device__ __forceinline__ void force_body(const Dev& d, const Consts& c, int bl
   // stored by list position (one load level instead of an index gather).
   // Positions past the list read entry kc instead: any entry in bounds
   // serves, since their sums are never stored.
-  ILane I;
+  ILane<kI> I;
   auto load_i = [&](int itile, int it, int ilane, int ilanes, int kc) {
 #pragma unroll
-    for (int q = 0; q < kIPerLane; ++q) {
+    for (int q = 0; q < kI; ++q) {
       I.pos[q] = itile * it + ilane + q * ilanes;
       const int k = min(I.pos[q], kc);
       I.g[q] = (kMaskSelf || kCentral) ? d.active[k] : 0;
@@ -534,7 +565,7 @@ __device__ __forceinline__ void force_body(const Dev& d, const Consts& c, int bl
   if (spec) {
     const int len1 = (n + c.s1 - 1) / c.s1;
     const int j0 = blk * len1, j1 = min(n, j0 + len1);
-    load_i(0, (kBlock >> c.lj1) * kIPerLane, tid >> c.lj1, kBlock >> c.lj1, n - 1);
+    load_i(0, (kBlock >> c.lj1) * kI, tid >> c.lj1, kBlock >> c.lj1, n - 1);
     if (j0 < j1) load_tile(j0, j1);
   }
 
@@ -567,7 +598,7 @@ __device__ __forceinline__ void force_body(const Dev& d, const Consts& c, int bl
       sj[6][tid] = rm;
       __syncthreads();
       if (jt + kTileJ < j1) load_tile(jt + kTileJ, j1);
-      tile_pairs<kMaskSelf, kMixed>(sj, cnt, LJ, jsub, jt, c.eps2, I);
+      tile_pairs<kMaskSelf, kMixed, kI>(sj, cnt, LJ, jsub, jt, c.eps2, I);
     }
     double bx = 0, by = 0, bz = 0, bvx = 0, bvy = 0, bvz = 0;
     if (kCentral) {
@@ -575,13 +606,13 @@ __device__ __forceinline__ void force_body(const Dev& d, const Consts& c, int bl
       bx = px[b]; by = py[b]; bz = pz[b];
       bvx = pvx[b]; bvy = pvy[b]; bvz = pvz[b];
     }
-    finish_item<kCentral>(d, c, LJ, jsub, slice, p.s, n_act, I, bx, by, bz, bvx, bvy, bvz);
+    finish_item<kCentral, kI>(d, c, LJ, jsub, slice, p.s, n_act, I, bx, by, bz, bvx, bvy, bvz);
   }
 }
 
-template <bool kMaskSelf, bool kCentral, bool kMixed>
+template <bool kMaskSelf, bool kCentral, bool kMixed, int kI>
 __global__ __launch_bounds__(kBlock) void k_force(Dev d, Consts c) {
-  force_body<kMaskSelf, kCentral, kMixed>(d, c, blockIdx.x, gridDim.x);
+  force_body<kMaskSelf, kCentral, kMixed, kI>(d, c, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -661,7 +692,7 @@ __device__ __forceinline__ void correct_body(const Dev& d, const Consts& c, int 
   // and below part_cs / s1, which every block with s1 slices satisfies).
   const int L1 = correct_lanes(c.s1);
   const int per1 = kBlock / L1;
-  const bool spec = blk * per1 < (kBlock >> c.lj1) * kIPerLane;
+  const bool spec = blk * per1 < (kBlock >> c.lj1) * c.ipl;
   const bool one_slot = c.s1 <= L1;
   int i = 0, lv = 0;
   double a0[3] = {0.0, 0.0, 0.0}, j0[3] = {0.0, 0.0, 0.0};
@@ -946,7 +977,7 @@ __device__ __forceinline__ void predict_body(const Dev& d, const Consts& c, int 
       kthr = kmax + 1;  // nobody active
     }
     Plan p{};
-    if (blk == 0 && nact > 0) p = make_plan_wave(nact, n, lane);
+    if (blk == 0 && nact > 0) p = make_plan_wave(nact, n, c.ipl, lane);
     if (lane == 0) {
       s_tnext = t_next;
       s_kthr = kthr;
@@ -1180,7 +1211,7 @@ __global__ void k_set_tend(Sched* __restrict__ sc, long long t_end) {
 }
 
 // Explicit active list for gd_force(idx, ...): range-checked copy.
-__global__ void k_set_active(Sched* __restrict__ sc, int n, const int32_t* __restrict__ idx,
+__global__ void k_set_active(Sched* __restrict__ sc, int n, int ipl, const int32_t* __restrict__ idx,
                              int n_act, int* __restrict__ active, const double* __restrict__ px,
                              const double* __restrict__ py, const double* __restrict__ pz,
                              const double* __restrict__ pvx, const double* __restrict__ pvy,
@@ -1192,7 +1223,7 @@ __global__ void k_set_active(Sched* __restrict__ sc, int n, const int32_t* __res
   if (k == 0) {
     sc->n_act = n_act;
     sc->done = 0;
-    sc->plan = make_plan(n_act, n);
+    sc->plan = make_plan(n_act, n, ipl);
   }
   if (k >= n_act) return;
   int i = idx[k];
@@ -1334,7 +1365,7 @@ __device__ __forceinline__ void pool_force_body(const PoolSlot* __restrict__ slo
   for (int g = blockIdx.x; g < total; g += gridDim.x) {
     const int k = pool_find(s_off, count, g);
     const PoolSlot& ps = slots[s_order[k]];
-    force_body<false, false, kMixed>(ps.d, ps.c, g - s_off[k], s_n[k]);
+    force_body<false, false, kMixed, kIPerLane>(ps.d, ps.c, g - s_off[k], s_n[k]);
   }
 }
 
@@ -1544,10 +1575,18 @@ hipError_t launch_predict(const Dev& d, const Consts& c, int mode, double t_expl
 
 hipError_t launch_force(const Dev& d, const Consts& c, hipStream_t s, hipEvent_t ev_start,
                         hipEvent_t ev_stop) {
-  auto kern = c.mixed ? (c.bh >= 0 ? k_force<false, true, true>
-                                    : (c.eps2 > 0.0 ? k_force<false, false, true> : k_force<true, false, true>))
-                      : (c.bh >= 0 ? k_force<false, true, false>
-                                   : (c.eps2 > 0.0 ? k_force<false, false, false> : k_force<true, false, false>));
+  // Four i per lane only with eps > 0 (no self mask): see make_consts.
+  auto kern = c.ipl == kIPerLaneLarge
+                  ? (c.mixed ? (c.bh >= 0 ? k_force<false, true, true, kIPerLaneLarge>
+                                          : k_force<false, false, true, kIPerLaneLarge>)
+                             : (c.bh >= 0 ? k_force<false, true, false, kIPerLaneLarge>
+                                          : k_force<false, false, false, kIPerLaneLarge>))
+              : c.mixed ? (c.bh >= 0 ? k_force<false, true, true, kIPerLane>
+                                     : (c.eps2 > 0.0 ? k_force<false, false, true, kIPerLane>
+                                                     : k_force<true, false, true, kIPerLane>))
+                        : (c.bh >= 0 ? k_force<false, true, false, kIPerLane>
+                                     : (c.eps2 > 0.0 ? k_force<false, false, false, kIPerLane>
+                                                     : k_force<true, false, false, kIPerLane>));
   if (ev_start) {
     // The events take the dispatch's own start and end timestamps.
     hipExtLaunchKernelGGL(kern, dim3(c.force_grid), dim3(kBlock), 0, s, ev_start, ev_stop, 0, d, c);
@@ -1602,7 +1641,7 @@ hipError_t launch_reset_sched(const Dev& d, long long t_now, hipStream_t s) {
 hipError_t launch_set_active(const Dev& d, const Consts& c, const int32_t* idx, int n_act,
                              hipStream_t s) {
   hipLaunchKernelGGL(k_set_active, dim3(grid_for(n_act > 0 ? n_act : 1)), dim3(kBlock), 0, s,
-                     d.sc, c.n, idx, n_act, d.active, d.px, d.py, d.pz, d.pvx, d.pvy, d.pvz, d.ix,
+                     d.sc, c.n, c.ipl, idx, n_act, d.active, d.px, d.py, d.pz, d.pvx, d.pvy, d.pvz, d.ix,
                      d.iy, d.iz, d.ivx, d.ivy, d.ivz);
   return hipGetLastError();
 }
