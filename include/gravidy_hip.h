@@ -89,8 +89,10 @@ typedef struct {
 } gd_stats;
 
 /*
- * Bytes of device workspace a context for n particles needs (n >= 2).
- * Host-only; no device work. p may be NULL (the size depends only on n).
+ * Bytes of device workspace a context for n particles with parameters p
+ * needs (n >= 2). Host-only; no device work. p may be NULL: the size is then
+ * the largest that any parameters need (it depends on n and, for large n,
+ * on whether eps > 0).
  */
 gd_status gd_workspace_bytes(int64_t n, const gd_params* p, size_t* bytes);
 

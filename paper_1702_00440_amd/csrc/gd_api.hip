@@ -49,7 +49,14 @@ struct Layout {
       part, ebuf, nact_log, total;
 };
 
-Layout make_layout(long long n) {
+// i particles per lane of a context's force kernel (see kIPerLaneLarge).
+int ipl_for(const gd_params* p, long long n) {
+  return (n >= kLargeN && p->eps > 0.0) ? kIPerLaneLarge : kIPerLane;
+}
+
+// The workspace of a context of n particles whose force kernel holds ipl i
+// per lane (pools use the size a context would have).
+Layout make_layout(long long n, int ipl) {
   Layout L;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -75,7 +82,7 @@ Layout make_layout(long long n) {
   for (int d = 0; d < 3; ++d) L.ia[d] = take(nd);
   for (int d = 0; d < 3; ++d) L.ij[d] = take(nd);
   L.ilev = take(sizeof(int) * (size_t)n);
-  L.part = take(sizeof(double) * 6 * (size_t)partial_rows(n));
+  L.part = take(sizeof(double) * 6 * (size_t)partial_rows(n, ipl));
   const long long eitems = std::max<long long>((n + kBlock - 1) / kBlock, kEnergyGrid);
   L.ebuf = take(sizeof(double) * 3 * (size_t)(eitems + 1));
   L.nact_log = take(sizeof(int) * 72);
@@ -163,13 +170,13 @@ Consts make_consts(const gd_params* p, int64_t n, int kmax, bool pool) {
   c.eps2 = p->eps * p->eps;
   c.bh = (int)p->bh_index;
   c.eps2_bh = p->bh_index >= 0 ? p->eps_bh * p->eps_bh : c.eps2;
-  c.ipl = (!pool && n >= kLargeN && p->eps > 0.0) ? kIPerLaneLarge : kIPerLane;
-  launch_grids((int)n, c.ipl, &c.force_grid, &c.correct_grid);
+  const int ipl = pool ? kIPerLane : ipl_for(p, n);
+  launch_grids((int)n, ipl, &c.force_grid, &c.correct_grid);
   c.mixed = (p->flags & GD_FLAG_MIXED) ? 1 : 0;
-  const Plan p1 = make_plan(1, (int)n, c.ipl);
-  c.lj1 = p1.lj;
+  const Plan p1 = make_plan(1, (int)n, ipl);
+  c.lj1_ipl = p1.lj | (ipl << 8);
   c.s1 = p1.s;
-  c.part_cs = partial_rows(n);
+  c.part_cs = partial_rows(n, ipl);
   return c;
 }
 
@@ -331,9 +338,9 @@ gd_status initialise(gd_ctx* c, const double* m, const double* x, const double* 
 extern "C" {
 
 gd_status gd_workspace_bytes(int64_t n, const gd_params* p, size_t* bytes) {
-  (void)p;
   if (!bytes || n < 2 || n > (int64_t)std::numeric_limits<int>::max() / 2) return GD_EINVAL;
-  *bytes = make_layout(n).total;
+  // Without parameters: the larger of the two sizes.
+  *bytes = make_layout(n, p ? ipl_for(p, n) : kIPerLaneLarge).total;
   return GD_OK;
 }
 
@@ -349,7 +356,7 @@ gd_status gd_init(gd_ctx** out, const gd_params* p, int64_t n, const double* m, 
   int kmax = 0;
   if (const char* why = check_params(p, n, &kmax)) return bad(GD_EINVAL, why);
   if (((uintptr_t)workspace & 255) != 0) return bad(GD_EINVAL, "workspace must be 256-byte aligned");
-  const Layout L = make_layout(n);
+  const Layout L = make_layout(n, ipl_for(p, n));
   if (ws_bytes < L.total) return bad(GD_ENOMEM, "workspace smaller than gd_workspace_bytes()");
 
   gd_ctx* c = new (std::nothrow) gd_ctx();
@@ -898,7 +905,7 @@ gd_status gd_pool_arena_bytes(int32_t max_clusters, const int64_t* n, int32_t co
   size_t b = pool_table_bytes(max_clusters);
   for (int k = 0; k < count; ++k) {
     if (n[k] < 2 || n[k] > (int64_t)std::numeric_limits<int>::max() / 2) return GD_EINVAL;
-    b += make_layout(n[k]).total;
+    b += make_layout(n[k], kIPerLaneLarge).total;
   }
   *bytes = b;
   return GD_OK;
@@ -971,7 +978,7 @@ gd_status gd_pool_admit(gd_pool* P, int64_t n, const double* m, const double* x,
       break;
     }
   if (sl < 0) return P->fail(GD_ENOMEM, "no free slot");
-  const Layout L = make_layout(n);
+  const Layout L = make_layout(n, ipl_for(&P->p, n));
   size_t off = 0;
   if (!pool_place(P, L.total, &off)) return P->fail(GD_ENOMEM, "no room in the arena");
   PoolSlotHost& s = P->slots[sl];

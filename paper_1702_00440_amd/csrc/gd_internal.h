@@ -115,12 +115,13 @@ __host__ __device__ inline Plan make_plan(int n_act, int n, int ipl) {
   }
 }
 
-// Rows of the partial-force buffer a context of n particles needs: for every
-// plan, s * n_act <= s * nit * it <= max(nit, kTargetItems) * it with
-// it <= 64 (either i count per lane), and s * n_act <= (n / kMinSlice
-// rounded up) * n. The size does not depend on the i count per lane.
-inline long long partial_rows(long long n) {
-  const long long it_max = (long long)(kBlock >> kMinLj) * kIPerLaneLarge;
+// Rows of the partial-force buffer a context of n particles with ipl i per
+// lane needs: for every plan, s * n_act <= s * nit * it <= max(nit,
+// kTargetItems) * it with it <= (kBlock >> kMinLj) * ipl, and
+// s * n_act <= (n / kMinSlice rounded up) * n. More i per lane never needs
+// fewer rows.
+inline long long partial_rows(long long n, int ipl) {
+  const long long it_max = (long long)(kBlock >> kMinLj) * ipl;
   const long long by_items = n + it_max + (long long)kTargetItems * it_max;
   const long long by_slices = ((n + kMinSlice - 1) / kMinSlice) * n;
   const long long rows = by_items < by_slices ? by_items : by_slices;
@@ -173,10 +174,15 @@ struct Consts {
   int mixed;         // 1: pair arithmetic in mixed precision (GD_FLAG_MIXED)
   double dt_min, dt_max, eta, eps2, eps2_bh;
   double inv_dt_min, inv_dt_max;  // exact reciprocals (powers of two)
-  int ipl;            // i particles per lane of the force kernel (kIPerLane or kIPerLaneLarge)
-  int lj1, s1;        // decomposition of a one-particle block: log2 lanes per i, j slices
-  long long part_cs;  // component stride of the partial-force buffer (partial_rows(n))
+  // The decomposition of a one-particle block (log2 lanes per i; j slices s1)
+  // and the force kernel's i count per lane, packed as lj1 | ipl << 8: one
+  // field more would split the corrector's kernel-argument loads into two
+  // dependent batches (its scalar registers are full).
+  int lj1_ipl, s1;
+  long long part_cs;  // component stride of the partial-force buffer (partial_rows(n, ipl))
 };
+__host__ __device__ inline int lj1_of(const Consts& c) { return c.lj1_ipl & 255; }
+__host__ __device__ inline int ipl_of(const Consts& c) { return c.lj1_ipl >> 8; }
 
 // Lanes the corrector gives one active particle: one per j slice of the
 // force plan (rounded up to a power of two), at most a wave.

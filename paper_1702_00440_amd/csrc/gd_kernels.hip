@@ -565,7 +565,8 @@ __device__ __forceinline__ void force_body(const Dev& d, const Consts& c, int bl
   if (spec) {
     const int len1 = (n + c.s1 - 1) / c.s1;
     const int j0 = blk * len1, j1 = min(n, j0 + len1);
-    load_i(0, (kBlock >> c.lj1) * kI, tid >> c.lj1, kBlock >> c.lj1, n - 1);
+    const int lj1 = lj1_of(c);
+    load_i(0, (kBlock >> lj1) * kI, tid >> lj1, kBlock >> lj1, n - 1);
     if (j0 < j1) load_tile(j0, j1);
   }
 
@@ -575,7 +576,7 @@ __device__ __forceinline__ void force_body(const Dev& d, const Consts& c, int bl
   const Plan p = sc->plan;
   if (blk >= p.items) return;
   // Same lanes per i and slices: same tile size, slice length and item map.
-  const bool early = spec && p.lj == c.lj1 && p.s == c.s1;
+  const bool early = spec && p.lj == lj1_of(c) && p.s == c.s1;
   const int LJ = 1 << p.lj;
   const int jsub = tid & (LJ - 1);
   const int ilane = tid >> p.lj;
@@ -692,7 +693,7 @@ __device__ __forceinline__ void correct_body(const Dev& d, const Consts& c, int 
   // and below part_cs / s1, which every block with s1 slices satisfies).
   const int L1 = correct_lanes(c.s1);
   const int per1 = kBlock / L1;
-  const bool spec = blk * per1 < (kBlock >> c.lj1) * c.ipl;
+  const bool spec = blk * per1 < (kBlock >> lj1_of(c)) * ipl_of(c);
   const bool one_slot = c.s1 <= L1;
   int i = 0, lv = 0;
   double a0[3] = {0.0, 0.0, 0.0}, j0[3] = {0.0, 0.0, 0.0};
@@ -977,7 +978,7 @@ __device__ __forceinline__ void predict_body(const Dev& d, const Consts& c, int 
       kthr = kmax + 1;  // nobody active
     }
     Plan p{};
-    if (blk == 0 && nact > 0) p = make_plan_wave(nact, n, c.ipl, lane);
+    if (blk == 0 && nact > 0) p = make_plan_wave(nact, n, ipl_of(c), lane);
     if (lane == 0) {
       s_tnext = t_next;
       s_kthr = kthr;
@@ -1576,7 +1577,7 @@ hipError_t launch_predict(const Dev& d, const Consts& c, int mode, double t_expl
 hipError_t launch_force(const Dev& d, const Consts& c, hipStream_t s, hipEvent_t ev_start,
                         hipEvent_t ev_stop) {
   // Four i per lane only with eps > 0 (no self mask): see make_consts.
-  auto kern = c.ipl == kIPerLaneLarge
+  auto kern = ipl_of(c) == kIPerLaneLarge
                   ? (c.mixed ? (c.bh >= 0 ? k_force<false, true, true, kIPerLaneLarge>
                                           : k_force<false, false, true, kIPerLaneLarge>)
                              : (c.bh >= 0 ? k_force<false, true, false, kIPerLaneLarge>
@@ -1641,7 +1642,7 @@ hipError_t launch_reset_sched(const Dev& d, long long t_now, hipStream_t s) {
 hipError_t launch_set_active(const Dev& d, const Consts& c, const int32_t* idx, int n_act,
                              hipStream_t s) {
   hipLaunchKernelGGL(k_set_active, dim3(grid_for(n_act > 0 ? n_act : 1)), dim3(kBlock), 0, s,
-                     d.sc, c.n, c.ipl, idx, n_act, d.active, d.px, d.py, d.pz, d.pvx, d.pvy, d.pvz, d.ix,
+                     d.sc, c.n, ipl_of(c), idx, n_act, d.active, d.px, d.py, d.pz, d.pvx, d.pvy, d.pvz, d.ix,
                      d.iy, d.iz, d.ivx, d.ivy, d.ivz);
   return hipGetLastError();
 }
