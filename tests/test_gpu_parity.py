@@ -298,6 +298,41 @@ def test_diagnostics_against_oracle(n):
     cl.close()
 
 
+def test_large_context_four_i_per_lane_against_oracle():
+    """Contexts of N >= 131072 (eps > 0) run the force kernel with four i per
+    lane: Plummer N = 131072, FP64. Sampled initial forces (512 random and the
+    32 innermost particles) within 1e-12 of the oracle's compensated sums; then
+    5 block steps from the GPU's state with the oracle's active set, times and
+    levels, and acceleration and jerk of the active particles within 1e-12."""
+    n = 131072
+    m, x, v = plummer(n, 9)
+    cl = g.Cluster(m, x, v, eta=ETA, eps=EPS, device=DEV)
+    _, _, a, j, _, _, _ = cl.state()
+    r = np.linalg.norm(x, axis=1)
+    idx = np.unique(np.concatenate([np.random.default_rng(4).choice(n, 512, replace=False), np.argsort(r)[:32]]))
+    ra, rj = oracle.force(m, x, v, EPS, idx=idx, compensated=True, threads=oracle.max_threads())
+    assert rel_err_rows(host(a)[idx], ra).max() <= F_TOL
+    assert rel_err_rows(host(j)[idx], rj).max() <= F_TOL
+    act = torch.empty(n, dtype=torch.int32, device=DEV)
+    for step in range(5):
+        xs, vs, a, j, t_i, dt_i, t_now = cl.state()
+        ref = oracle.State.from_arrays(m, host(xs), host(vs), host(a), host(j), host(t_i), host(dt_i), t_now,
+                                       EPS, ETA, DTMAX, DTMIN, threads=oracle.max_threads())
+        act_ref = ref.block_step()
+        g.gd_predict(cl.ctx)
+        n_act = g.gd_active(cl.ctx, act)
+        np.testing.assert_array_equal(np.sort(host(act[:n_act])), act_ref)
+        g.gd_force(cl.ctx)
+        g.gd_correct(cl.ctx)
+        xs, vs, a, j, t_i, dt_i, t_now = cl.state()
+        assert t_now == ref.t_now
+        np.testing.assert_array_equal(host(t_i), ref.t_i)
+        np.testing.assert_array_equal(host(dt_i), ref.dt_i)
+        assert rel_err_rows(host(a)[act_ref], ref.a[act_ref]).max() <= F_TOL
+        assert rel_err_rows(host(j)[act_ref], ref.jk[act_ref]).max() <= F_TOL
+    cl.close()
+
+
 def test_nact_histogram_against_oracle():
     """Block steps by active-block size (bin b: 2^b <= N_act < 2^(b+1)) over
     Plummer N = 1024 to t = 1/8 equal the histogram of the oracle's own
