@@ -55,6 +55,33 @@ def test_workspace_bytes_host_only():
     assert e.value.status == g.GD_EINVAL
 
 
+def test_workspace_bytes_follow_items_per_lane():
+    # Contexts of 131072 or more softened particles hold four i per lane, which
+    # needs a larger partial-force buffer; NULL parameters give the larger size.
+    big = 131072
+    soft = g.make_params(eps=1e-4)
+    hard = g.make_params(eps=0.0)
+    b_soft = g.gd_workspace_bytes(big, soft)
+    b_hard = g.gd_workspace_bytes(big, hard)
+    assert b_soft > b_hard
+    assert g.gd_workspace_bytes(big) == b_soft
+    assert g.gd_workspace_bytes(big - 1, soft) == g.gd_workspace_bytes(big - 1, hard)
+    assert g.gd_workspace_bytes(big - 1) >= g.gd_workspace_bytes(big - 1, soft)
+
+
+def test_init_rejects_workspace_sized_for_two_i_per_lane():
+    lib = g.library()
+    n = 131072
+    p = g.make_params(eps=1e-4)
+    short = g.gd_workspace_bytes(n, g.make_params(eps=0.0))
+    assert short < g.gd_workspace_bytes(n, p)
+    ctx = C.c_void_p()
+    dummy = C.c_void_p(256)
+    rc = lib.gd_init(C.byref(ctx), C.byref(p), n, dummy, dummy, dummy, dummy, short, None)
+    assert rc == g.GD_ENOMEM
+    assert "workspace" in g.gd_last_error(None)
+
+
 @pytest.mark.parametrize("kw,msg", [
     (dict(eta=0.0), "eta"),
     (dict(eta=float("nan")), "eta"),
