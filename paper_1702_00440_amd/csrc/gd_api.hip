@@ -83,7 +83,8 @@ Layout make_layout(long long n, int ipl) {
   for (int d = 0; d < 3; ++d) L.ij[d] = take(nd);
   L.ilev = take(sizeof(int) * (size_t)n);
   L.part = take(sizeof(double) * 6 * (size_t)partial_rows(n, ipl));
-  const long long eitems = std::max<long long>((n + kBlock - 1) / kBlock, kEnergyGrid);
+  // At least kEnergyGrid entries: the diagnostics reuse the buffer for their results.
+  const long long eitems = std::max<long long>(make_eplan((int)n).items, kEnergyGrid);
   L.ebuf = take(sizeof(double) * 3 * (size_t)(eitems + 1));
   L.nact_log = take(sizeof(int) * 72);
   L.total = off;

@@ -35,7 +35,11 @@ constexpr int kMinSlice = kTileJ;
 // (kBlock >> kMinLj) * ipl = 32 (or 64) particles, which keeps the number of
 // j slices (and so the partial sums to reduce) small for large blocks.
 constexpr int kMinLj = 4;
-// Energy: fixed grid of slice items.
+// Energy: i particles per lane from kEnergyLargeN particles on (one below,
+// where four would leave most lanes idle), and the nominal number of
+// workgroups a call is split into.
+constexpr int kEnergyIPerLane = 4;
+constexpr int kEnergyLargeN = 16384;
 constexpr int kEnergyGrid = 1024;
 // Maximum block-step level (dt = dt_max / 2^level).
 constexpr int kMaxLevels = 41;
@@ -129,19 +133,23 @@ inline long long partial_rows(long long n, int ipl) {
   return rows > n + 16 ? rows : n + 16;
 }
 
-// Energy decomposition: items are (i tile of kBlock, j slice).
+// Energy decomposition: items are (i tile of kBlock * ipl, j slice). Slices
+// are whole LDS tiles; about 8 items per workgroup of the nominal grid keep
+// the tail of the launch short.
 struct EPlan {
-  int nit, s, len, items;
+  int ipl, nit, s, len, items;
 };
 __host__ __device__ inline EPlan make_eplan(int n) {
   EPlan e;
-  e.nit = (n + kBlock - 1) / kBlock;
-  int max_s = (n + kTileJ - 1) / kTileJ;
-  int s = kEnergyGrid / e.nit;
+  e.ipl = n >= kEnergyLargeN ? kEnergyIPerLane : 1;
+  const int tile = kBlock * e.ipl;
+  e.nit = (n + tile - 1) / tile;
+  const int max_s = (n + kTileJ - 1) / kTileJ;
+  int s = (8 * kEnergyGrid + e.nit - 1) / e.nit;
   if (s > max_s) s = max_s;
   if (s < 1) s = 1;
   e.s = s;
-  e.len = (n + s - 1) / s;
+  e.len = (((n + s - 1) / s + kTileJ - 1) / kTileJ) * kTileJ;
   e.items = e.nit * s;
   return e;
 }
@@ -161,7 +169,7 @@ struct Dev {
   double *iax, *iay, *iaz, *ijx, *ijy, *ijz;  // a, jerk at t_i of the active list, by position
   int* ilev;                               // level of the active list, by position
   double* part;                            // [6][partial_rows(n)]: position * s + slot
-  double* ebuf;                            // energy partials [kEnergyGrid][3] + result [3]
+  double* ebuf;                            // energy partials [items][3] + result [3]
   int* nact_log;                           // force-timing pass: N_act of each timed step
 };
 

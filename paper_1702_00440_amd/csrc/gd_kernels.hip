@@ -1039,12 +1039,54 @@ __global__ __launch_bounds__(kBlock) void k_predict(Dev d, Consts c, int mode, d
 // Energy (Eq. (2), softened and unsoftened potentials)
 // ---------------------------------------------------------------------------
 //
-// Items are (i tile of 256, j slice); each lane sums phi_i over its slice
-// with the j = i term excluded, then the workgroup reduces -m_i phi_i / 2
-// (and the kinetic term, on slice 0) in a fixed tree. A second kernel sums
-// the item partials in a fixed order.
+// The potential sums each pair once: a lane holds kI i particles
+// (EPlan::ipl) and sums phi_i = sum_{j > i} m_j / sqrt(r_ij^2 + eps_ij^2)
+// over the j of its item (i tile, j slice); the workgroup then reduces
+// -m_i phi_i (and the kinetic term, on slice 0) in a fixed tree, and a second
+// kernel sums the item partials in a fixed order. Tiles wholly left of the i
+// tile are skipped and only those that overlap it test j > i. The central
+// particle's column enters the tile with mass 0 and is added once for each
+// i below it, with its own softening, by the slice that holds it.
+template <int kI, bool kMask, bool kUnsoft>
+__device__ __forceinline__ void energy_tile(const double (*sj)[4], int cnt, int jt,
+                                            const int (&ii)[kI],
+                                            const double (&xi)[kI],
+                                            const double (&yi)[kI],
+                                            const double (&zi)[kI],
+                                            const double (&e2)[kI],
+                                            double (&phi)[kI],
+                                            double (&phiu)[kI]) {
+#pragma unroll 2
+  for (int k = 0; k < cnt; ++k) {
+    const double2 xy = *reinterpret_cast<const double2*>(&sj[k][0]);
+    const double2 zm = *reinterpret_cast<const double2*>(&sj[k][2]);
+#pragma unroll
+    for (int q = 0; q < kI; ++q) {
+      const double dx = xy.x - xi[q], dy = xy.y - yi[q], dz = zm.x - zi[q];
+      double r2 = 0.0, s2;
+      if constexpr (kUnsoft) {
+        r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+        s2 = r2 + e2[q];
+      } else {
+        s2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2[q])));
+      }
+      double mj = zm.y;
+      if constexpr (kMask) {
+        const bool lower = jt + k <= ii[q];
+        s2 = lower ? 1.0 : s2;
+        mj = lower ? 0.0 : mj;
+      }
+      phi[q] = fma(mj, rsqrt_fp64(s2), phi[q]);
+      if constexpr (kUnsoft) {
+        const double u2 = kMask && jt + k <= ii[q] ? 1.0 : r2;
+        phiu[q] = fma(mj, rsqrt_fp64(u2), phiu[q]);
+      }
+    }
+  }
+}
+
+template <int kI, bool kUnsoft>
 __global__ __launch_bounds__(kBlock) void k_energy(int n, double eps2, double eps2_bh, int bh,
-                                                   int unsoft,
                                                    const double* __restrict__ x,
                                                    const double* __restrict__ y,
                                                    const double* __restrict__ z,
@@ -1054,42 +1096,60 @@ __global__ __launch_bounds__(kBlock) void k_energy(int n, double eps2, double ep
                                                    const double* __restrict__ m,
                                                    double* __restrict__ ebuf) {
   const EPlan e = make_eplan(n);
-  __shared__ double sj[4][kTileJ];
+  __shared__ __align__(16) double sj[kTileJ][4];
   __shared__ double red[3][kBlock];
   const int tid = threadIdx.x;
   for (int item = blockIdx.x; item < e.items; item += gridDim.x) {
-    const int itile = item / e.s, slice = item - itile * e.s;
-    const int i = itile * kBlock + tid;
-    const int j0 = slice * e.len, j1 = min(n, j0 + e.len);
-    const int ii = min(i, n - 1);
-    const double xi = x[ii], yi = y[ii], zi = z[ii];
-    double phi = 0.0, phiu = 0.0;
-    for (int jt = j0; jt < j1; jt += kTileJ) {
+    // The slice is rotated by the i tile: consecutive workgroups go to
+    // different XCDs, and under j > i the slices hold unequal work.
+    const int itile = item / e.s, slice = (item - itile * e.s + itile) % e.s;
+    const int i0 = itile * kBlock * kI;
+    const int j0 = min(n, slice * e.len), j1 = min(n, j0 + e.len);
+    int ii[kI];
+    double xi[kI], yi[kI], zi[kI], e2[kI], phi[kI], phiu[kI];
+#pragma unroll
+    for (int q = 0; q < kI; ++q) {
+      ii[q] = min(i0 + q * kBlock + tid, n - 1);
+      xi[q] = x[ii[q]]; yi[q] = y[ii[q]]; zi[q] = z[ii[q]];
+      e2[q] = ii[q] == bh ? eps2_bh : eps2;
+      phi[q] = 0.0; phiu[q] = 0.0;
+    }
+    // i0 and j0 are multiples of kTileJ, so max(j0, i0) starts a tile.
+    for (int jt = max(j0, i0); jt < j1; jt += kTileJ) {
       const int cnt = min(kTileJ, j1 - jt);
       __syncthreads();
       if (tid < cnt) {
-        sj[0][tid] = x[jt + tid];
-        sj[1][tid] = y[jt + tid];
-        sj[2][tid] = z[jt + tid];
-        sj[3][tid] = m[jt + tid];
+        const int j = jt + tid;
+        *reinterpret_cast<double2*>(&sj[tid][0]) = make_double2(x[j], y[j]);
+        *reinterpret_cast<double2*>(&sj[tid][2]) = make_double2(z[j], j == bh ? 0.0 : m[j]);
       }
       __syncthreads();
-      for (int k = 0; k < cnt; ++k) {
-        const double dx = sj[0][k] - xi, dy = sj[1][k] - yi, dz = sj[2][k] - zi;
-        const bool self = (jt + k) == ii;
+      if (jt < i0 + kBlock * kI)
+        energy_tile<kI, true, kUnsoft>(sj, cnt, jt, ii, xi, yi, zi, e2, phi, phiu);
+      else
+        energy_tile<kI, false, kUnsoft>(sj, cnt, jt, ii, xi, yi, zi, e2, phi, phiu);
+    }
+    if (bh >= j0 && bh < j1) {
+      const double xb = x[bh], yb = y[bh], zb = z[bh], mb = m[bh];
+#pragma unroll
+      for (int q = 0; q < kI; ++q) {
+        if (ii[q] >= bh) continue;
+        const double dx = xb - xi[q], dy = yb - yi[q], dz = zb - zi[q];
         const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-        const double mj = self ? 0.0 : sj[3][k];
-        const double e2 = (bh >= 0 && ((jt + k) == bh || ii == bh)) ? eps2_bh : eps2;
-        phi = fma(mj, rsqrt_fp64(self ? 1.0 : r2 + e2), phi);
-        if (unsoft) phiu = fma(mj, rsqrt_fp64(self ? 1.0 : r2), phiu);
+        phi[q] = fma(mb, rsqrt_fp64(r2 + eps2_bh), phi[q]);
+        if constexpr (kUnsoft) phiu[q] = fma(mb, rsqrt_fp64(r2), phiu[q]);
       }
     }
     double kin = 0.0, pot = 0.0, potu = 0.0;
-    if (i < n) {
-      const double mi = m[i];
-      pot = -0.5 * mi * phi;
-      potu = -0.5 * mi * phiu;
-      if (slice == 0) kin = 0.5 * mi * fma(vz[i], vz[i], fma(vy[i], vy[i], vx[i] * vx[i]));
+#pragma unroll
+    for (int q = 0; q < kI; ++q) {
+      const int i = i0 + q * kBlock + tid;
+      if (i < n) {
+        const double mi = m[i];
+        pot -= mi * phi[q];
+        potu -= mi * phiu[q];
+        if (slice == 0) kin += 0.5 * mi * fma(vz[i], vz[i], fma(vy[i], vy[i], vx[i] * vx[i]));
+      }
     }
     red[0][tid] = kin;
     red[1][tid] = pot;
@@ -1614,11 +1674,14 @@ hipError_t launch_reduce_out(const Dev& d, const Consts& c, double* acc, double*
 }
 
 hipError_t launch_energy(const Dev& d, const Consts& c, int unsoft, hipStream_t s) {
-  hipLaunchKernelGGL(k_energy, dim3(kEnergyGrid), dim3(kBlock), 0, s, c.n, c.eps2, c.eps2_bh, c.bh,
-                     unsoft, d.x, d.y, d.z, d.vx, d.vy, d.vz, d.m, d.ebuf);
+  const EPlan ep = make_eplan(c.n);
+  auto kern = ep.ipl == kEnergyIPerLane ? (unsoft ? k_energy<kEnergyIPerLane, true>
+                                                  : k_energy<kEnergyIPerLane, false>)
+                                        : (unsoft ? k_energy<1, true> : k_energy<1, false>);
+  hipLaunchKernelGGL(kern, dim3(ep.items), dim3(kBlock), 0, s, c.n, c.eps2, c.eps2_bh, c.bh, d.x,
+                     d.y, d.z, d.vx, d.vy, d.vz, d.m, d.ebuf);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const EPlan ep = make_eplan(c.n);
   hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kBlock), 0, s, c.n, d.ebuf,
                      d.ebuf + 3 * (size_t)ep.items);
   return hipGetLastError();

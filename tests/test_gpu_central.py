@@ -132,3 +132,25 @@ def test_full_size_sampled(flags, tol):
             for i in diff:
                 assert dt_gpu[i] in (2.0 * ref.dt_i[i], 0.5 * ref.dt_i[i])
     cl.close()
+
+
+@pytest.mark.parametrize("ns,bh", [(20000, 7777), (16383, 16383), (16383, 0)])
+def test_energy_with_central_particle_anywhere(ns, bh):
+    """Energy (Eq. (2)) with the central particle at any index, both
+    potentials: 20001 particles (four i per lane in the energy kernel, a
+    ragged last i tile) and 16384 (the smallest such context), with the
+    particle moved to the given index. Against the oracle to 1e-12."""
+    m, x, v = plummer_with_bh(ns, 9)
+    order = np.concatenate([np.arange(bh), [ns], np.arange(bh, ns)])
+    m, x, v = m[order], x[order], v[order]
+    cl = g.Cluster(m, x, v, eta=ETA, eps=EPS, dt_max=DTMAX, dt_min=DTMIN, device=DEV, eps_bh=EPS_BH,
+                   bh_index=bh)
+    ek, ep, eu = g.gd_energy(cl.ctx, unsoftened=True)
+    rk, rp, ru = oracle.energy(m, x, v, EPS, unsoftened=True, eps_bh=EPS_BH, bh=bh)
+    assert ek == pytest.approx(rk, rel=1e-12)
+    assert ep == pytest.approx(rp, rel=1e-12)
+    assert eu == pytest.approx(ru, rel=1e-12)
+    # the central particle's pairs matter at this tolerance: eps instead of eps_bh fails
+    _, rp_plain = oracle.energy(m, x, v, EPS)
+    assert abs(rp_plain - rp) > 1e-10 * abs(rp)
+    cl.close()
