@@ -43,6 +43,9 @@ MUTATIONS = [
     ("doubling ignores block alignment", "fmod(t_new, 2.0 * dt_old) == 0.0", "1"),
     ("quantisation rounds up", "while (cand > dtstar && cand >= dt_min) cand *= 0.5;",
      "while (cand > 2.0 * dtstar && cand >= dt_min) cand *= 0.5;"),
+    ("Neumaier branch swapped", "if (fabs(*s) >= fabs(x))", "if (fabs(*s) < fabs(x))"),
+    ("Neumaier compensation sign", "*c += (*s - t) + x;", "*c -= (*s - t) + x;"),
+    ("compensation dropped from the force sums", "acc[d] = s_acc[d] + c_acc[d];", "acc[d] = s_acc[d];"),
     ("active set misses ties", "if (t_i[i] + dt_i[i] == t_next) active_out[n_act++] = i;",
      "if (t_i[i] + dt_i[i] == t_next && n_act == 0) active_out[n_act++] = i;"),
 ]
@@ -65,6 +68,7 @@ PIN_CALLS = [
     lambda: pins.test_quantize_rules(),
     lambda: pins.test_block_scheduler_invariants(),
     lambda: pins.test_central_particle_softening(),
+    lambda: pins.test_compensated_sum_ill_conditioned(64, 1),
 ]
 
 

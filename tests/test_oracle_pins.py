@@ -192,6 +192,77 @@ def test_bruteforce_decimal(n, eps, seed):
     assert ep == pytest.approx(dp, rel=1e-14)
 
 
+def _cancelling_system(n_light, seed, d=1e-3):
+    """Particle 0 at rest at the origin between two heavy particles placed
+    point-symmetrically about it (x = +-d, v = +-(0, 1, 0)), first and last
+    in index order, with light particles (masses about 1e-6) on the +x side.
+    The heavy pair's acceleration and jerk terms on particle 0 are exact
+    negatives of each other in FP64 (negation is exact), so the exact sums
+    are the light particles' alone, about 1e-10 and 1e-13 of the sum of the
+    terms' magnitudes."""
+    rng = np.random.default_rng(seed)
+    n = n_light + 3
+    m = np.empty(n)
+    x = np.zeros((n, 3))
+    v = np.zeros((n, 3))
+    m[0] = 0.5
+    m[1], x[1], v[1] = 1.0, [d, 0.0, 0.0], [0.0, 1.0, 0.0]
+    m[-1], x[-1], v[-1] = 1.0, [-d, 0.0, 0.0], [0.0, -1.0, 0.0]
+    m[2:-1] = 1e-6 * rng.uniform(0.5, 1.5, n_light)
+    x[2:-1, 0] = rng.uniform(0.5, 1.5, n_light)
+    x[2:-1, 1:] = rng.uniform(-0.5, 0.5, (n_light, 2))
+    v[2:-1] = rng.normal(size=(n_light, 3))
+    return m, x, v
+
+
+def _decimal_row(m, x, v, eps, i):
+    """Acceleration and jerk of particle i at 50 digits, with the sums of the
+    terms' magnitudes."""
+    getcontext().prec = 50
+    D = lambda a: Decimal(repr(float(a)))
+    acc, jrk = [Decimal(0)] * 3, [Decimal(0)] * 3
+    sa, sj = [Decimal(0)] * 3, [Decimal(0)] * 3
+    for j in range(len(m)):
+        if j == i:
+            continue
+        r = [D(x[j][k]) - D(x[i][k]) for k in range(3)]
+        w = [D(v[j][k]) - D(v[i][k]) for k in range(3)]
+        s = sum(c * c for c in r) + D(eps) * D(eps)
+        rs = s.sqrt()
+        rw = sum(r[k] * w[k] for k in range(3))
+        for k in range(3):
+            ta = D(m[j]) * r[k] / (s * rs)
+            tj = D(m[j]) * (w[k] / (s * rs) - 3 * rw * r[k] / (s * s * rs))
+            acc[k] += ta
+            jrk[k] += tj
+            sa[k] += abs(ta)
+            sj[k] += abs(tj)
+    f = lambda L: np.array([float(c) for c in L])
+    return f(acc), f(jrk), f(sa), f(sj)
+
+
+@pytest.mark.parametrize("n_light,seed", [(64, 1), (200, 2)])
+def test_compensated_sum_ill_conditioned(n_light, seed):
+    """The compensated force mode (the reference that every GPU parity test
+    uses) against 50-digit sums of Eq. (3) and its time derivative on a sum
+    that cancels by ten orders of magnitude: within 1e-14 of the exact
+    acceleration and jerk, while plain FP64 summation of the same terms in
+    the same order loses at least five digits."""
+    m, x, v = _cancelling_system(n_light, seed)
+    da, dj, sa, sj = _decimal_row(m, x, v, 0.0, 0)
+    kappa_a = sa.sum() / np.linalg.norm(da)
+    kappa_j = sj.sum() / np.linalg.norm(dj)
+    assert kappa_a > 1e9 and kappa_j > 1e12
+    ca, cj = oracle.force(m, x, v, 0.0, idx=[0], compensated=True)
+    pa, pj = oracle.force(m, x, v, 0.0, idx=[0], compensated=False)
+    rel = lambda got, ref: np.linalg.norm(got[0] - ref) / np.linalg.norm(ref)
+    assert rel(ca, da) <= 1e-14 and rel(cj, dj) <= 1e-14
+    assert rel(pa, da) >= 1e-8 and rel(pj, dj) >= 1e-5
+    # a few ulps of the terms' magnitudes, component by component
+    u = 2.0 ** -53
+    assert np.all(np.abs(ca[0] - da) <= 4 * u * sa) and np.all(np.abs(cj[0] - dj) <= 4 * u * sj)
+
+
 def test_central_particle_softening():
     """A central massive particle softened with its own eps_bh (pairs that
     involve it use eps_bh, all others eps): m a = -grad U with the same rule;
@@ -467,6 +538,28 @@ def test_energy_drift_n1024_paper_level():
     assert 0.5 < s.stats[0] / final["iter"] < 2.0
     assert 0.5 < s.stats[1] / final["nsteps"] < 2.0
     assert s.stats[2] == s.stats[1] * 1024
+
+
+@pytest.mark.slow
+def test_energy_drift_above_target_is_truncation_error():
+    """Plummer N = 1024, seed 2 (eps 1e-4, dt_max 1/8, to t = 1) drifts
+    1.9e-6 at eta = 0.01, above the 1e-6 bound, in one jump during the first
+    1/8 time unit (a close encounter). The error is the integrator's
+    truncation error, not rounding or a mistake: it falls at least fourfold
+    per halving of eta (a fourth-order scheme's global error scales as
+    dt^4, and the time-step criterion makes dt scale as eta^(1/2)), while
+    rounding error would not shrink with smaller steps."""
+    m, x, v = plummer(1024, 2)
+    drift, first = [], []
+    for eta in (0.01, 0.005, 0.0025):
+        s = oracle.State(m, x, v, 1e-4, eta, 0.125, 2.0 ** -22, threads=oracle.max_threads())
+        rows = s.run(1.0)
+        drift.append(rows[:, 5].max())
+        first.append(rows[0, 5])
+    assert drift[0] > 1e-6
+    assert first[0] > 0.9 * drift[0]
+    assert drift[1] <= drift[0] / 4 and drift[2] <= drift[1] / 4, drift
+    assert drift[2] < 1e-8
 
 
 def test_energy_error_grows_with_eta():
