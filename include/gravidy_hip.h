@@ -55,7 +55,8 @@ typedef enum {
 
 typedef struct {
   double eta;        /* time-step accuracy parameter (Sec. 3.2; paper default 0.01), > 0 */
-  double eps;        /* Plummer softening length (Eq. (3); paper default 1e-4); 0 or >= 1e-30 */
+  double eps;        /* Plummer softening length (Eq. (3); paper default 1e-4); 0 or >= 1e-30
+                        (>= 1e-10 with GD_FLAG_MIXED) */
   double eps_bh;     /* softening of every pair that involves the central particle */
   double dt_max;     /* largest block step, a power of two (e.g. 0.125) */
   double dt_min;     /* smallest block step, a power of two <= dt_max (e.g. 2^-22) */
@@ -104,11 +105,12 @@ gd_status gd_workspace_bytes(int64_t n, const gd_params* p, size_t* bytes);
  * largest dt_max / 2^k <= dt*, clamped at dt_min); the initial energy (read
  * by gd_stats as e0). Synchronises the stream.
  * Errors: GD_EINVAL for n < 2, a NULL pointer, eta <= 0, eps outside
- * {0} U [1e-30, inf), dt_max/dt_min not powers of two or dt_min > dt_max,
- * log2(dt_max/dt_min) > 40, flags other than 0 or GD_FLAG_MIXED, a bad
- * central-particle setting, or non-finite m/x/v or m < 0 (checked on the
- * device); GD_ENOMEM if ws_bytes is too small; GD_EHIP on HIP failure. On
- * error *ctx is NULL.
+ * {0} U [1e-30, inf) (with GD_FLAG_MIXED: {0} U [1e-10, inf), since the
+ * self pair's m / eps^3 is rounded to FP32), dt_max/dt_min not powers of two
+ * or dt_min > dt_max, log2(dt_max/dt_min) > 40, flags other than 0 or
+ * GD_FLAG_MIXED, a bad central-particle setting, or non-finite m/x/v or
+ * m < 0 (checked on the device); GD_ENOMEM if ws_bytes is too small; GD_EHIP
+ * on HIP failure. On error *ctx is NULL.
  */
 gd_status gd_init(gd_ctx** ctx, const gd_params* p, int64_t n, const double* m, const double* x,
                   const double* v, void* workspace, size_t ws_bytes, void* hip_stream);

@@ -153,6 +153,10 @@ const char* check_params(const gd_params* p, int64_t n, int* kmax_out) {
   const int kmax = (int)std::lround(std::log2(p->dt_max / p->dt_min));
   if (kmax > 40) return "log2(dt_max / dt_min) must be <= 40";
   if ((p->flags & ~GD_FLAG_MIXED) != 0) return "flags: unknown bits";
+  // Mixed precision rounds m q^3 of the softened self pair (q = 1 / eps) to
+  // FP32; below eps^2 = 1e-20 it would overflow, and inf * 0 gives NaN.
+  if ((p->flags & GD_FLAG_MIXED) && p->eps > 0.0 && p->eps * p->eps < 1e-20)
+    return "with GD_FLAG_MIXED, eps must be 0 or have eps^2 >= 1e-20";
   *kmax_out = kmax;
   return nullptr;
 }

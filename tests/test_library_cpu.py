@@ -91,6 +91,8 @@ def test_init_rejects_workspace_sized_for_two_i_per_lane():
     (dict(dt_min=0.25), "power"),
     (dict(dt_min=2.0 ** -60), "40"),
     (dict(flags=2), "flags"),
+    (dict(flags=g.GD_FLAG_MIXED, eps=1e-11), "eps^2 >= 1e-20"),
+    (dict(flags=g.GD_FLAG_MIXED, eps=5e-11), "eps^2 >= 1e-20"),
 ])
 def test_init_rejects_bad_params_before_any_device_work(kw, msg):
     """Parameter validation happens on the host before any HIP call, so it can
@@ -103,6 +105,18 @@ def test_init_rejects_bad_params_before_any_device_work(kw, msg):
     assert rc == g.GD_EINVAL
     assert not ctx.value
     assert msg in g.gd_last_error(None)
+
+
+def test_mixed_softening_bound_accepts_zero_and_1e_minus_10():
+    """GD_FLAG_MIXED takes eps = 0 (the self pair is masked) and eps^2 >=
+    1e-20; those pass the host checks and stop only at the workspace size."""
+    lib = g.library()
+    ctx = C.c_void_p()
+    dummy = C.c_void_p(256)
+    for eps in (0.0, 1e-10, 1e-4):
+        p = g.make_params(flags=g.GD_FLAG_MIXED, eps=eps)
+        rc = lib.gd_init(C.byref(ctx), C.byref(p), 16, dummy, dummy, dummy, dummy, 1, None)
+        assert rc == g.GD_ENOMEM, eps
 
 
 def test_init_rejects_short_workspace_and_null():
