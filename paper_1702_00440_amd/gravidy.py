@@ -24,6 +24,11 @@ _NAMES = {GD_EINVAL: "GD_EINVAL", GD_ENOMEM: "GD_ENOMEM", GD_EHIP: "GD_EHIP",
           GD_ESTATE: "GD_ESTATE", GD_ENONFINITE: "GD_ENONFINITE"}
 
 
+def status_name(status: int) -> str:
+    """Name of a gd_status value ("GD_OK", "GD_EINVAL", ...)."""
+    return "GD_OK" if status == GD_OK else _NAMES.get(status, str(status))
+
+
 class GdError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"{_NAMES.get(status, status)}: {message}")

@@ -155,25 +155,56 @@ def test_block_step_parity_from_identical_state(n):
     cl.close()
 
 
-def test_full_run_n1024_against_oracle():
-    """Plummer N = 1024 to t = 1 (eps 1e-4, eta 0.01, dt_max 1/8): same number
-    of block and particle steps, energy drift under 1e-6, final state close
-    (the trajectories separate only through rounding over 1 time unit)."""
+@pytest.mark.parametrize("seed,within_target", [(1, True), (2, False), (3, True)])
+def test_full_run_n1024_against_oracle(seed, within_target):
+    """Plummer N = 1024 to t = 1 (eps 1e-4, eta 0.01, dt_max 1/8), seeds 1-3:
+    same number of block, particle and pair steps and clamps, the energy of
+    every synchronised time equal to the oracle's, final state close (the
+    trajectories separate only through rounding over 1 time unit). The energy
+    drift meets 1e-6 for seeds 1 and 3; seed 2 drifts 1.9e-6 in both, from
+    one close encounter at eta = 0.01 (truncation error: the oracle's drift
+    falls about a hundredfold per halving of eta, pinned on the CPU)."""
     n = 1024
-    m, x, v = plummer(n, 1)
+    m, x, v = plummer(n, seed)
     cl = g.Cluster(m, x, v, eta=ETA, eps=EPS, device=DEV)
-    st = g.gd_step_to(cl.ctx, 1.0)
-    ref = oracle.State(m, x, v, EPS, ETA, DTMAX, DTMIN, threads=8)
+    ref = oracle.State(m, x, v, EPS, ETA, DTMAX, DTMIN, threads=oracle.max_threads())
     rows = ref.run(1.0)
+    e_gpu = []
+    for k in range(1, 9):
+        e_gpu.append(g.gd_step_to(cl.ctx, k * DTMAX)["e"])
+    st = g.gd_stats_get(cl.ctx)
     assert st["t"] == 1.0
     assert st["block_steps"] == ref.stats[0]
     assert st["particle_steps"] == ref.stats[1]
     assert st["pair_interactions"] == ref.stats[2]
     assert st["dtmin_clamps"] == ref.stats[3]
-    assert abs(st["e"] - st["e0"]) / abs(st["e0"]) < 1e-6
-    assert st["e"] == pytest.approx(rows[-1, 3], rel=1e-11)
+    np.testing.assert_allclose(e_gpu, rows[:, 3], rtol=1e-11)
+    drift = max(abs(e - st["e0"]) for e in e_gpu) / abs(st["e0"])
+    assert drift == pytest.approx(rows[:, 5].max(), rel=1e-3, abs=1e-10)
+    assert (drift <= 1e-6) == within_target
     xs = host(cl.state()[0])
     assert np.abs(xs - ref.x).max() < 1e-8
+    cl.close()
+
+
+def _poisoned(n, seed):
+    """A Plummer sphere whose particle 7 moves at 1e290: its initial force is
+    finite, but one dt_min later its distances square to infinity and every
+    jerk of the first block step is NaN (the oracle gives the same)."""
+    m, x, v = plummer(n, seed)
+    v = v.copy()
+    v[7] = [1e290, 0.0, 0.0]
+    return m, x, v
+
+
+def test_nonfinite_force_is_reported_by_a_context():
+    m, x, v = _poisoned(300, 5)
+    cl = g.Cluster(m, x, v, eta=ETA, eps=EPS, device=DEV)
+    _, _, a, j, _, _, _ = cl.state()
+    assert torch.isfinite(a).all() and torch.isfinite(j).all()
+    with pytest.raises(g.GdError) as e:
+        g.gd_step_to(cl.ctx, 0.125)
+    assert e.value.status == g.GD_ENONFINITE
     cl.close()
 
 

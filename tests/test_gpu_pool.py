@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 import torch
 
+import oracle
 from paper_1702_00440_amd import gravidy as g
 from paper_1702_00440_amd import serving
 from synth_inputs import plummer
@@ -111,3 +112,150 @@ def test_serving_loop_staggered_arrivals():
         assert r.done >= r.admitted >= r.arrival - 1e-6
         np.testing.assert_array_equal(host(r.x), host(seq[r.rid].x))
         assert r.stats["block_steps"] == seq[r.rid].stats["block_steps"]
+
+
+def _c4_clusters(count):
+    """The first `count` requests of the serving workload: N log-uniform in
+    [256, 8192] from numpy's PCG64 seeded 2024, equal-mass Plummer spheres
+    seeded 1000 + k (the first six have N = 2664, 538, 748, 4088, 8074, 419)."""
+    rng = np.random.default_rng(2024)
+    out = []
+    for k in range(count):
+        n = int(round(np.exp(rng.uniform(np.log(256), np.log(8192)))))
+        out.append((n, 1000 + k))
+    return out
+
+
+def _run_pool(sizes, t_end, flags=0, extra=()):
+    """Admits every (n, seed) cluster (plus `extra` (m, x, v) host arrays) into
+    one pool, drains it, and returns {index: (status, x, v, stats)}."""
+    p = g.make_params(flags=flags, **PARAMS)
+    ics = [plummer(n, seed) for n, seed in sizes] + list(extra)
+    arena = torch.empty(g.gd_pool_arena_bytes(len(ics), [len(m) for m, _, _ in ics]), dtype=torch.uint8,
+                        device=DEV)
+    pool = g.gd_pool_create(p, len(ics), arena)
+    slot_of = {}
+    for k, (m, x, v) in enumerate(ics):
+        slot_of[g.gd_pool_admit(pool, dev(m), dev(x), dev(v), t_end)] = k
+    assert g.gd_pool_resident(pool) == len(ics)
+    finished = _drain(pool)
+    assert sorted(finished) == sorted(slot_of)
+    out = {}
+    for sl, k in slot_of.items():
+        n = len(ics[k][0])
+        xo = torch.empty(n, 3, dtype=torch.float64, device=DEV)
+        vo = torch.empty_like(xo)
+        try:
+            st = g.gd_pool_result(pool, sl, xo, vo)
+            out[k] = ("GD_OK", host(xo), host(vo), st)
+        except g.GdError as e:
+            out[k] = (g.status_name(e.status), None, None, None)
+        g.gd_pool_release(pool, sl)
+    g.gd_pool_destroy(pool)
+    return out
+
+
+def test_pool_c4_shape_against_oracle():
+    """Six clusters drawn as the serving workload draws them (N from 419 to
+    8074), integrated together in one FP64 pool to t = 0.5, each against the
+    oracle's own integration of the same cluster: identical block, particle
+    and pair counts and dt_min clamps; energy at t = 0 and t = 0.5 within
+    1e-10; final positions within 1e-9; energy drift of each solve within
+    1e-6 per time unit (the bound of the survey's reading of the paper's
+    Sec. 3.2 energy conservation), as the oracle's own is."""
+    sizes = _c4_clusters(6)
+    assert max(n for n, _ in sizes) > 8000
+    res = _run_pool(sizes, 0.5)
+    for k, (n, seed) in enumerate(sizes):
+        status, xg, _, st = res[k]
+        assert status == "GD_OK"
+        m, x, v = plummer(n, seed)
+        ref = oracle.State(m, x, v, PARAMS["eps"], PARAMS["eta"], PARAMS["dt_max"], PARAMS["dt_min"],
+                           threads=oracle.max_threads())
+        rows = ref.run(0.5)
+        got = (st["block_steps"], st["particle_steps"], st["pair_interactions"], st["dtmin_clamps"])
+        assert got == tuple(int(c) for c in ref.stats), (n, got, ref.stats)
+        assert st["t"] == 0.5
+        assert st["e0"] == pytest.approx(ref.e0, rel=1e-10)
+        assert st["e"] == pytest.approx(rows[-1, 3], rel=1e-10)
+        dx = np.abs(xg - ref.x).max()
+        assert dx < 1e-9, (n, dx)
+        drift = abs(st["e"] - st["e0"]) / abs(st["e0"])
+        assert drift <= 1e-6, (n, drift)
+        print(f"n={n}: steps {got[0]}, drift {drift:.2e} (oracle {rows[-1, 5]:.2e}), max|dx| {dx:.1e}")
+
+
+def test_mixed_pool_c4_shape_against_fp64_pool():
+    """The same six clusters in a mixed-precision pool: each solve's energy
+    drift within 1e-6, and block and particle steps within 2 % of the FP64
+    pool's (the trajectories differ at the mixed precision's error level)."""
+    sizes = _c4_clusters(6)
+    f64 = _run_pool(sizes, 0.5)
+    mix = _run_pool(sizes, 0.5, flags=g.GD_FLAG_MIXED)
+    for k, (n, _) in enumerate(sizes):
+        sm, sf = mix[k][3], f64[k][3]
+        drift = abs(sm["e"] - sm["e0"]) / abs(sm["e0"])
+        assert drift <= 1e-6, (n, drift)
+        assert abs(sm["block_steps"] - sf["block_steps"]) <= 0.02 * sf["block_steps"]
+        assert abs(sm["particle_steps"] - sf["particle_steps"]) <= 0.02 * sf["particle_steps"]
+
+
+def _poisoned(n, seed):
+    """A Plummer sphere whose particle 7 moves at 1e290: its initial force is
+    finite (the cluster is admitted), but one dt_min later its distances
+    square to infinity and every jerk of the first block step is NaN (the
+    oracle gives the same)."""
+    m, x, v = plummer(n, seed)
+    v = v.copy()
+    v[7] = [1e290, 0.0, 0.0]
+    return m, x, v
+
+
+def test_pool_retires_nonfinite_cluster_others_bitwise():
+    """A cluster whose forces turn non-finite during the run is retired with
+    GD_ENONFINITE; the clusters packed with it finish bitwise as alone."""
+    sizes = [(256, 31), (700, 32), (1024, 33)]
+    res = _run_pool(sizes, 0.25, extra=[_poisoned(300, 34)])
+    assert res[3][0] == "GD_ENONFINITE"
+    for k, (n, seed) in enumerate(sizes):
+        status, xg, vg, st = res[k]
+        assert status == "GD_OK"
+        xa, va, sa = _alone(n, seed, 0.25)
+        np.testing.assert_array_equal(xg, xa)
+        np.testing.assert_array_equal(vg, va)
+        assert st["block_steps"] == sa["block_steps"] and st["e"] == sa["e"]
+
+
+def test_serving_loop_failed_requests_do_not_stop_others():
+    """The request loop records failed requests with their status and serves
+    the rest: a request with a NaN position (GD_EINVAL at admission), one
+    whose forces turn non-finite (GD_ENONFINITE when retired) and one larger
+    than the whole arena (GD_ENOMEM); the others match sequential solves
+    bitwise."""
+    p = g.make_params(**PARAMS)
+    reqs = []
+    for k, n in enumerate([256, 512, 777, 300]):
+        m, x, v = _ics(n, 200 + k)
+        reqs.append(serving.Request(k, 0.0, m, x, v, 0.125))
+    m, x, v = plummer(300, 204)
+    x = x.copy()
+    x[3, 0] = np.nan
+    reqs.append(serving.Request(4, 0.0, dev(m), dev(x), dev(v), 0.125))
+    m, x, v = _poisoned(300, 205)
+    reqs.append(serving.Request(5, 0.0, dev(m), dev(x), dev(v), 0.125))
+    m, x, v = _ics(4096, 206)
+    reqs.append(serving.Request(6, 0.0, m, x, v, 0.125))
+    srv = serving.PoolServer(p, 4, g.gd_pool_arena_bytes(4, [1024] * 4), keep_state=True)
+    res = {r.rid: r for r in srv.serve(reqs)}
+    srv.close()
+    assert sorted(res) == list(range(7))
+    assert res[4].status == "GD_EINVAL"
+    assert res[5].status == "GD_ENONFINITE"
+    assert res[6].status == "GD_ENOMEM"
+    seq = {r.rid: r for r in serving.serve_sequential(p, reqs[:4], keep_state=True)}
+    for k in range(4):
+        assert res[k].ok
+        np.testing.assert_array_equal(host(res[k].x), host(seq[k].x))
+        assert res[k].stats["block_steps"] == seq[k].stats["block_steps"]
+    bad = serving.serve_sequential(p, reqs[4:6])
+    assert [r.status for r in bad] == ["GD_EINVAL", "GD_ENONFINITE"]
