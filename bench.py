@@ -34,6 +34,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 FLOPS_PER_PAIR = 60
+# Relative energy drift allowed per N-body time unit (the bound taken for the
+# paper's Sec. 3.2 energy conservation): max_k |E_k - E_0| / |E_0| at the
+# synchronised times, against 1e-6 * max(1, t_end).
+DRIFT_TARGET_PER_TIME = 1e-6
 PEAK_FP64_VECTOR_TFLOPS = 78.6
 PEAK_FP32_VECTOR_TFLOPS = 157.3
 
@@ -137,6 +141,49 @@ def cpu_baseline(w, seconds):
     }
 
 
+def full_force_imf(warmup, steps):
+    """One O(N^2) force and jerk evaluation (N_act = N) of the mixed-precision
+    workload's sphere (Plummer N = 262144, power-law IMF, eps 1e-4), in FP64
+    and in mixed precision: the force launch of gd_reinit timed with its own
+    HIP events (gd_profile_force), `steps` times after `warmup`; pair
+    interactions per second, achieved FLOP/s at 60 flops per pair against
+    the FP64 and FP32 vector peaks, and the largest per-particle relative
+    difference of the mixed forces from the FP64 ones on the same state."""
+    import torch
+
+    from paper_1702_00440_amd import gravidy as g
+    from synth_inputs import WORKLOADS, plummer_imf
+
+    w = WORKLOADS["plummer_imf_n262144"]
+    n = w["n"]
+    dev = torch.device("cuda:0")
+    m, x, v = plummer_imf(n, w["seed"])
+    md, xd, vd = (torch.as_tensor(a).to(dev).contiguous() for a in (m, x, v))
+    out, forces = {}, {}
+    for mode, flags in (("fp64", 0), ("mixed", g.GD_FLAG_MIXED)):
+        cl = g.Cluster(m, x, v, eta=w["eta"], eps=w["eps"], dt_max=w["dt_max"], dt_min=w["dt_min"],
+                       device=dev, flags=flags)
+        for _ in range(warmup):
+            g.gd_reinit(cl.ctx, md, xd, vd)
+        g.gd_profile_force(cl.ctx, True)
+        for _ in range(steps):
+            g.gd_reinit(cl.ctx, md, xd, vd)
+        prof = g.gd_profile_get(cl.ctx)
+        g.gd_profile_force(cl.ctx, False)
+        forces[mode] = cl.state()[2:4]
+        cl.close()
+        sec = prof["force_ms"] / 1e3 / prof["launches"]
+        tf = FLOPS_PER_PAIR * n * n / sec / 1e12
+        out[mode] = {"pairs_per_s": n * n / sec, "kernel_ms": sec * 1e3, "launches": prof["launches"],
+                     "achieved_tflops": tf, "frac_fp64_peak": tf / PEAK_FP64_VECTOR_TFLOPS,
+                     "frac_fp32_peak": tf / PEAK_FP32_VECTOR_TFLOPS}
+    out["mixed_vs_fp64_max_rel_diff"] = {"acc": _rel_rows(forces["mixed"][0], forces["fp64"][0]),
+                                         "jerk": _rel_rows(forces["mixed"][1], forces["fp64"][1])}
+    out["workload"] = "plummer_imf_n262144 full force (N_act = N = 262144), eps 1e-4, seed 5"
+    out["timing"] = "HIP events around each force launch (hipExtLaunchKernelGGL), average over launches"
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -146,6 +193,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the force-launch event timing")
+    ap.add_argument("--no-full-force", action="store_true",
+                    help="skip the N = 262144 full-force figures (FP64 and mixed) of the default line")
     ap.add_argument("--kernel-hash", action="store_true",
                     help="print the hash of the kernel sources that a counter summary is tied to")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -286,6 +335,8 @@ def main():
             "ic": "equal-mass Plummer sphere (Aarseth-Henon-Wielen sampling), Henon units",
         },
         "energy_drift": drift,
+        "energy_drift_target": DRIFT_TARGET_PER_TIME * max(1.0, t_end),
+        "energy_drift_within_target": drift <= DRIFT_TARGET_PER_TIME * max(1.0, t_end),
         "block_steps": stats["block_steps"],
         "particle_steps": stats["particle_steps"],
         "pairs_per_step": stats["pair_interactions"] + n * n,
@@ -306,9 +357,11 @@ def main():
         },
         "force_by_n_act": by_nact,
     }
+    cl.close()
+    if not args.no_full_force:
+        out["full_force_n262144"] = full_force_imf(1, 3)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
-    cl.close()
     print(json.dumps(out), flush=True)
 
 
