@@ -336,8 +336,43 @@ gd_status gd_nact_histogram(gd_ctx* c, int64_t* counts);
 /* Free the host-side context (not the workspace, which the caller owns). NULL is a no-op. */
 void gd_destroy(gd_ctx* c);
 
-/* Message for the last failing call on c (c may be NULL: then the last gd_init failure). */
+/* Message for the last failing call on c (c may be NULL: then the last
+ * failure of gd_init or gd_force_noalloc on this thread). */
 const char* gd_last_error(const gd_ctx* c);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * acceleration and jerk that gd_force computes for an index list, from the
+ * caller's arrays, with no context and no workspace. The call allocates
+ * nothing. Its intermediate arrays (the j stream, the listed particles'
+ * state, the slice partials and the schedule record) live in one scratch
+ * array of the library per GPU, about 11.3 MiB, held from the library's
+ * first use on that GPU until the process ends; the first call on a device
+ * looks up that device's copy.
+ *   p          parameters, validated as in gd_init; eps, eps_bh, bh_index and
+ *              GD_FLAG_MIXED select the pair arithmetic
+ *   n          particles, 2 <= n <= GD_NOALLOC_MAX_N
+ *   m          device, n masses
+ *   x, v       device, (n, 3) positions and velocities, all at one time
+ *   idx        device, n_act int32 indices (repeats allowed); an index outside
+ *              [0, n) gives NaN output rows
+ *   n_act      0 <= n_act <= n; 0 queues nothing
+ *   acc, jerk  device, (n_act, 3) outputs in list order; either may be NULL
+ *   hip_stream the stream (on the current device) that the work is queued on;
+ *              the call does not synchronise, so it may be captured
+ * Results are bitwise those of gd_force(c, idx, n_act, acc, jerk) on a context
+ * of the same n and parameters whose predicted state is (x, v).
+ * Calls on one GPU share its scratch array and every call rewrites it: calls
+ * whose work is not ordered (different streams with no dependency between
+ * them) race and give wrong results. Calls on one stream are ordered.
+ * Errors (message in gd_last_error(NULL)): GD_EINVAL for invalid parameters,
+ * n or n_act out of range, or a NULL array when n_act > 0; GD_EHIP.
+ */
+#define GD_NOALLOC_MAX_N 65536
+gd_status gd_force_noalloc(const gd_params* p, int64_t n, const double* m, const double* x,
+                           const double* v, const int32_t* idx, int64_t n_act, double* acc,
+                           double* jerk, void* hip_stream);
 
 #ifdef __cplusplus
 }

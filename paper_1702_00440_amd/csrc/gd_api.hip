@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <algorithm>
 #include <string>
 #include <vector>
@@ -161,9 +162,9 @@ const char* check_params(const gd_params* p, int64_t n, int* kmax_out) {
   return nullptr;
 }
 
-// Constants of a context (pool == false) or of a pool's cluster (pool ==
-// true: pools run the force kernel with kIPerLane i per lane).
-Consts make_consts(const gd_params* p, int64_t n, int kmax, bool pool) {
+// Constants of n particles whose force kernel holds ipl i per lane, without
+// the launch grids.
+Consts consts_of(const gd_params* p, int64_t n, int kmax, int ipl) {
   Consts c{};
   c.n = (int)n;
   c.kmax = kmax;
@@ -175,13 +176,21 @@ Consts make_consts(const gd_params* p, int64_t n, int kmax, bool pool) {
   c.eps2 = p->eps * p->eps;
   c.bh = (int)p->bh_index;
   c.eps2_bh = p->bh_index >= 0 ? p->eps_bh * p->eps_bh : c.eps2;
-  const int ipl = pool ? kIPerLane : ipl_for(p, n);
-  launch_grids((int)n, ipl, &c.force_grid, &c.correct_grid);
   c.mixed = (p->flags & GD_FLAG_MIXED) ? 1 : 0;
   const Plan p1 = make_plan(1, (int)n, ipl);
   c.lj1_ipl = p1.lj | (ipl << 8);
   c.s1 = p1.s;
   c.part_cs = partial_rows(n, ipl);
+  return c;
+}
+
+// Constants of a context (pool == false) or of a pool's cluster (pool ==
+// true: pools run the force kernel with kIPerLane i per lane), with launch
+// grids for every block size.
+Consts make_consts(const gd_params* p, int64_t n, int kmax, bool pool) {
+  const int ipl = pool ? kIPerLane : ipl_for(p, n);
+  Consts c = consts_of(p, n, kmax, ipl);
+  launch_grids((int)n, ipl, &c.force_grid, &c.correct_grid);
   return c;
 }
 
@@ -761,6 +770,202 @@ void gd_destroy(gd_ctx* c) {
 const char* gd_last_error(const gd_ctx* c) {
   if (!c) return g_init_error.c_str();
   return c->err.c_str();
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Force evaluation without device allocation (gd_force_noalloc)
+// ===========================================================================
+//
+// The arrays a context keeps in its workspace for one force evaluation (the
+// schedule record, the j stream, the listed particles' state and the slice
+// partials) live here in one file-scope device array per GPU. Host code never
+// uses the array's name as an address: the first call on a device resolves
+// that device's copy with hipGetSymbolAddress and keeps the pointer.
+
+namespace {
+
+constexpr long long kNoallocMaxN = GD_NOALLOC_MAX_N;
+
+constexpr size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Byte offsets of the arrays of one call with n particles.
+struct NoallocLayout {
+  size_t sc, jm, p[3], pv[3], active, ip[3], ipv[3], part, total;
+};
+
+constexpr NoallocLayout noalloc_layout(long long n) {
+  NoallocLayout L{};
+  size_t off = 0;
+  const size_t nd = sizeof(double) * (size_t)n;
+  L.sc = off;
+  off = align256(off + sizeof(Sched));
+  L.jm = off;
+  off = align256(off + nd);
+  for (int d = 0; d < 3; ++d) {
+    L.p[d] = off;
+    off = align256(off + nd);
+  }
+  for (int d = 0; d < 3; ++d) {
+    L.pv[d] = off;
+    off = align256(off + nd);
+  }
+  L.active = off;
+  off = align256(off + sizeof(int) * (size_t)n);
+  for (int d = 0; d < 3; ++d) {
+    L.ip[d] = off;
+    off = align256(off + nd);
+  }
+  for (int d = 0; d < 3; ++d) {
+    L.ipv[d] = off;
+    off = align256(off + nd);
+  }
+  L.part = off;
+  off = align256(off + sizeof(double) * 6 * (size_t)partial_rows(n, kIPerLane));
+  L.total = off;
+  return L;
+}
+
+// Every size up to the maximum fits: each offset grows with n.
+constexpr size_t kNoallocScratchBytes = noalloc_layout(kNoallocMaxN).total;
+static_assert(kNoallocMaxN < kLargeN, "calls of this size hold two i per lane, as contexts do");
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// This device's copy of the scratch array (resolved once per device).
+gd_status noalloc_scratch(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    g_init_error = std::string("current device: ") + hipGetErrorString(e);
+    return GD_EHIP;
+  }
+  if (dev < 0 || dev >= kMaxDevices) {
+    g_init_error = "device ordinal beyond the library's table";
+    return GD_EINVAL;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      g_init_error = std::string("scratch address: ") + hipGetErrorString(e);
+      return GD_EHIP;
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return GD_OK;
+}
+
+}  // namespace
+
+// The inputs of one gd_force_noalloc call in the force kernel's layout: the
+// j stream (structure of arrays; masses with the central particle's zeroed),
+// the listed particles' state by list position, and the schedule record of a
+// step with those n_act particles. A listed index outside [0, n) gives its
+// position a NaN state (so NaN output rows) and the list entry -1.
+__global__ void k_noalloc_load(Dev d, int n, int bh, int ipl, const double* __restrict__ m,
+                               const double* __restrict__ x, const double* __restrict__ v,
+                               const int32_t* __restrict__ idx, int n_act) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0) {
+    Sched* sc = d.sc;
+    sc->n_act = n_act;
+    sc->done = 0;
+    sc->nonfinite = 0;
+    sc->bad_input = 0;
+    sc->plan = make_plan(n_act, n, ipl);
+  }
+  if (t < n) {
+    d.px[t] = x[3 * t]; d.py[t] = x[3 * t + 1]; d.pz[t] = x[3 * t + 2];
+    d.pvx[t] = v[3 * t]; d.pvy[t] = v[3 * t + 1]; d.pvz[t] = v[3 * t + 2];
+    if (bh >= 0) d.jm[t] = t == bh ? 0.0 : m[t];
+  }
+  if (t < n_act) {
+    const int i = idx[t];
+    const bool ok = i >= 0 && i < n;
+    const int k = ok ? i : 0;
+    const double nan = __builtin_nan("");
+    d.active[t] = ok ? i : -1;
+    d.ix[t] = ok ? x[3 * k] : nan;
+    d.iy[t] = ok ? x[3 * k + 1] : nan;
+    d.iz[t] = ok ? x[3 * k + 2] : nan;
+    d.ivx[t] = ok ? v[3 * k] : nan;
+    d.ivy[t] = ok ? v[3 * k + 1] : nan;
+    d.ivz[t] = ok ? v[3 * k + 2] : nan;
+  }
+}
+
+extern "C" {
+
+gd_status gd_force_noalloc(const gd_params* p, int64_t n, const double* m, const double* x,
+                           const double* v, const int32_t* idx, int64_t n_act, double* acc,
+                           double* jerk, void* hip_stream) {
+  auto bad = [](gd_status st, const char* msg) {
+    g_init_error = msg;
+    return st;
+  };
+  if (!p) return bad(GD_EINVAL, "NULL parameters");
+  int kmax = 0;
+  if (const char* why = check_params(p, n, &kmax)) return bad(GD_EINVAL, why);
+  if (n > kNoallocMaxN) return bad(GD_EINVAL, "n exceeds GD_NOALLOC_MAX_N (65536)");
+  if (n_act < 0 || n_act > n) return bad(GD_EINVAL, "n_act out of range");
+  if (n_act == 0) return GD_OK;
+  if (!m || !x || !v || !idx) return bad(GD_EINVAL, "NULL argument");
+  void* base = nullptr;
+  GD_TRY(noalloc_scratch(&base));
+
+  const NoallocLayout L = noalloc_layout(n);
+  char* w = (char*)base;
+  Dev d{};
+  d.sc = (Sched*)(w + L.sc);
+  d.m = const_cast<double*>(m);  // read only
+  d.jm = (double*)(w + L.jm);
+  d.px = (double*)(w + L.p[0]);
+  d.py = (double*)(w + L.p[1]);
+  d.pz = (double*)(w + L.p[2]);
+  d.pvx = (double*)(w + L.pv[0]);
+  d.pvy = (double*)(w + L.pv[1]);
+  d.pvz = (double*)(w + L.pv[2]);
+  d.active = (int*)(w + L.active);
+  d.ix = (double*)(w + L.ip[0]);
+  d.iy = (double*)(w + L.ip[1]);
+  d.iz = (double*)(w + L.ip[2]);
+  d.ivx = (double*)(w + L.ipv[0]);
+  d.ivy = (double*)(w + L.ipv[1]);
+  d.ivz = (double*)(w + L.ipv[2]);
+  d.part = (double*)(w + L.part);
+
+  // The constants of a context of this size; the grids follow this call's
+  // own decomposition (the kernels' results do not depend on the grid).
+  Consts c = consts_of(p, n, kmax, kIPerLane);
+  const Plan plan = make_plan((int)n_act, (int)n, kIPerLane);
+  c.force_grid = std::min(plan.items, kForceGrid);
+  const long long lanes = n_act * correct_lanes(plan.s);
+  c.correct_grid = (int)std::min<long long>((lanes + kBlock - 1) / kBlock, kCorrectGrid);
+
+  hipStream_t s = (hipStream_t)hip_stream;
+  const int grid = (int)((n + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_noalloc_load, dim3(grid), dim3(kBlock), 0, s, d, (int)n, c.bh, kIPerLane, m, x,
+                     v, idx, (int)n_act);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = launch_force(d, c, s);
+  if (e == hipSuccess) e = launch_reduce_out(d, c, acc, jerk, s);
+  if (e != hipSuccess) {
+    g_init_error = std::string("force launch: ") + hipGetErrorString(e);
+    return GD_EHIP;
+  }
+  return GD_OK;
 }
 
 }  // extern "C"

@@ -124,7 +124,7 @@ __host__ __device__ inline Plan make_plan(int n_act, int n, int ipl) {
 // kTargetItems) * it with it <= (kBlock >> kMinLj) * ipl, and
 // s * n_act <= (n / kMinSlice rounded up) * n. More i per lane never needs
 // fewer rows.
-inline long long partial_rows(long long n, int ipl) {
+constexpr long long partial_rows(long long n, int ipl) {
   const long long it_max = (long long)(kBlock >> kMinLj) * ipl;
   const long long by_items = n + it_max + (long long)kTargetItems * it_max;
   const long long by_slices = ((n + kMinSlice - 1) / kMinSlice) * n;

@@ -104,6 +104,8 @@ def library():
     lib.gd_destroy.restype = None
     lib.gd_last_error.argtypes = [_VP]
     lib.gd_last_error.restype = C.c_char_p
+    lib.gd_force_noalloc.argtypes = [C.POINTER(gd_params), i64, _VP, _VP, _VP, _VP, i64, _VP, _VP, _VP]
+    lib.gd_force_noalloc.restype = st
     _lib = lib
     return lib
 
@@ -206,6 +208,22 @@ def gd_force(ctx, idx=None, acc=None, jerk=None) -> None:
     n_act = 0 if idx is None else idx.shape[0]
     _check(library().gd_force(ctx, _ptr(idx, torch.int32, None, "idx"), n_act,
                               _ptr(acc, torch.float64, None, "acc"), _ptr(jerk, torch.float64, None, "jerk")), ctx)
+
+
+GD_NOALLOC_MAX_N = 65536
+
+
+def gd_force_noalloc(params: gd_params, m, x, v, idx, acc=None, jerk=None, stream=None) -> None:
+    """Acceleration and jerk of the listed particles without a context or any
+    device allocation (the library's scratch array); queued, not synchronised."""
+    n = m.shape[0]
+    n_act = idx.shape[0]
+    rc = library().gd_force_noalloc(C.byref(params), n, _ptr(m, torch.float64, (n,), "m"),
+                                    _ptr(x, torch.float64, (n, 3), "x"), _ptr(v, torch.float64, (n, 3), "v"),
+                                    _ptr(idx, torch.int32, (n_act,), "idx"), n_act,
+                                    _ptr(acc, torch.float64, (n_act, 3), "acc"),
+                                    _ptr(jerk, torch.float64, (n_act, 3), "jerk"), _stream_handle(stream))
+    _check(rc, None)
 
 
 def gd_active(ctx, idx=None) -> int:

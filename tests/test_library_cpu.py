@@ -171,3 +171,18 @@ def test_pool_create_validation_host_only():
         rc = lib.gd_pool_create(C.byref(pool), C.byref(p), mc, dummy, 1 << 30, None)
         assert rc == g.GD_EINVAL, (kw, mc)
     assert g.gd_pool_arena_bytes(4, [256, 512]) > g.gd_workspace_bytes(256) + g.gd_workspace_bytes(512)
+
+
+def test_force_noalloc_checks_sizes_on_the_host():
+    """gd_force_noalloc rejects sizes beyond its scratch array, and an empty
+    list, before any device work (so these answer without a GPU)."""
+    lib = g.library()
+    p = g.make_params()
+    rc = lib.gd_force_noalloc(C.byref(p), g.GD_NOALLOC_MAX_N + 1, None, None, None, None, 4, None, None, None)
+    assert rc == g.GD_EINVAL
+    assert b"GD_NOALLOC_MAX_N" in lib.gd_last_error(None)
+    assert lib.gd_force_noalloc(C.byref(p), 1000, None, None, None, None, 1001, None, None, None) == g.GD_EINVAL
+    assert lib.gd_force_noalloc(C.byref(p), 1000, None, None, None, None, -1, None, None, None) == g.GD_EINVAL
+    assert lib.gd_force_noalloc(C.byref(p), 1000, None, None, None, None, 0, None, None, None) == g.GD_OK
+    bad = g.make_params(eps=-1.0)
+    assert lib.gd_force_noalloc(C.byref(bad), 1000, None, None, None, None, 4, None, None, None) == g.GD_EINVAL
