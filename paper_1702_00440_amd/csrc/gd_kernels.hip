@@ -64,23 +64,25 @@ __device__ __forceinline__ void pair_fp64(double xi, double yi, double zi, doubl
   A.jz = fma(mq3, wz, A.jz);
 }
 
-// FP32 accumulators of one i particle over one LDS tile (mixed precision).
-struct Acc6f {
-  float ax, ay, az, jx, jy, jz;
+// FP32 acceleration sums of one i particle over one LDS tile (mixed precision).
+struct Acc3f {
+  float ax, ay, az;
 };
 
-// The same pair in mixed precision. The scalar factors are FP64: the
-// differences r = x_j - x_i and w = v_j - v_i, s = r.r + eps^2, r.w, and
-// q = s^(-1/2) from v_rsq_f64 with one Newton step y (3 - s y^2) / 2 (about
-// 2^-47, ample for the FP32 results); m q^3 and -3 (r.w) q^2 are then rounded
-// to FP32 once each. The vector terms m q^3 r and m q^3 (w - 3 (r.w) q^2 r)
-// are formed and summed in FP32 from r and w rounded to FP32; the caller
-// folds the FP32 sums of each tile into FP64 accumulators. (Rounding q
-// itself to FP32 before forming q^2 and q^3 would dominate the jerk error.)
+// The same pair in mixed precision: the acceleration terms in FP32, the jerk
+// in FP64. The scalar factors are FP64: the differences r = x_j - x_i and
+// w = v_j - v_i, s = r.r + eps^2, r.w, and q = s^(-1/2) from v_rsq_f64 with
+// one Newton step y (3 - s y^2) / 2 (relative error about 2^-47). m q^3 and r
+// are rounded to FP32 once each; the acceleration terms m q^3 r are formed
+// and summed in FP32 over each LDS tile (at most 256 / LJ terms per lane),
+// and the caller adds the tile sums into FP64 accumulators. The jerk terms
+// m q^3 (w - 3 (r.w) q^2 r) are formed and accumulated in FP64: a particle's
+// jerk sum can cancel by two orders of magnitude, and FP32 terms (each
+// rounded to about 6e-8 of its size) then miss a relative error of 2e-6.
 __device__ __forceinline__ void pair_mixed(double xi, double yi, double zi, double vxi, double vyi,
                                            double vzi, double xj, double yj, double zj, double vxj,
                                            double vyj, double vzj, double mj, double eps2,
-                                           Acc6f& A) {
+                                           Acc6& A, Acc3f& F) {
   const double dx = xj - xi, dy = yj - yi, dz = zj - zi;
   const double dvx = vxj - vxi, dvy = vyj - vyi, dvz = vzj - vzi;
   const double s = fma(dz, dz, fma(dy, dy, fma(dx, dx, eps2)));
@@ -88,17 +90,16 @@ __device__ __forceinline__ void pair_mixed(double xi, double yi, double zi, doub
   const double y = __builtin_amdgcn_rsq(s);
   const double q = fma(y * fma(-s, y * y, 1.0), 0.5, y);
   const double q2 = q * q;
-  const float mq3 = (float)((mj * q) * q2);
-  const float b3 = (float)((rv * q2) * -3.0);
-  const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
-  const float fvx = (float)dvx, fvy = (float)dvy, fvz = (float)dvz;
-  A.ax = fmaf(mq3, fx, A.ax);
-  A.ay = fmaf(mq3, fy, A.ay);
-  A.az = fmaf(mq3, fz, A.az);
-  const float wx = fmaf(b3, fx, fvx), wy = fmaf(b3, fy, fvy), wz = fmaf(b3, fz, fvz);
-  A.jx = fmaf(mq3, wx, A.jx);
-  A.jy = fmaf(mq3, wy, A.jy);
-  A.jz = fmaf(mq3, wz, A.jz);
+  const double mq3 = (mj * q) * q2;
+  const double b3 = (rv * q2) * -3.0;
+  const float fm = (float)mq3;
+  F.ax = fmaf(fm, (float)dx, F.ax);
+  F.ay = fmaf(fm, (float)dy, F.ay);
+  F.az = fmaf(fm, (float)dz, F.az);
+  const double wx = fma(b3, dx, dvx), wy = fma(b3, dy, dvy), wz = fma(b3, dz, dvz);
+  A.jx = fma(mq3, wx, A.jx);
+  A.jy = fma(mq3, wy, A.jy);
+  A.jz = fma(mq3, wz, A.jz);
 }
 
 // Value held by lane (lane ^ kOff) of the wave, kOff in {1, 2, 4, 8, 16, 32},
@@ -352,7 +353,7 @@ struct ILane {
   double vx[kI], vy[kI], vz[kI], e2[kI];
   int g[kI], pos[kI];
   Acc6 A[kI];
-  Acc6f Af[kI];  // mixed precision: sums of the current tile
+  Acc3f Af[kI];  // mixed precision: acceleration sums of the current tile
 };
 
 // Pairs of one LDS tile of cnt j (first index jt). Lane jsub of each group of
@@ -365,7 +366,7 @@ __device__ __forceinline__ void tile_pairs(const double (*sj)[kTileJ], int cnt, 
   const int full = cnt & ~(LJ - 1);
   if (kMixed) {
 #pragma unroll
-    for (int q = 0; q < kI; ++q) I.Af[q] = Acc6f{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int q = 0; q < kI; ++q) I.Af[q] = Acc3f{0.f, 0.f, 0.f};
   }
   auto pairs_with = [&](int k) {
     const double xj = sj[0][k], yj = sj[1][k], zj = sj[2][k];
@@ -379,7 +380,7 @@ __device__ __forceinline__ void tile_pairs(const double (*sj)[kTileJ], int cnt, 
       const double xjq = self ? I.x[q] + 1.0 : xj;
       if (kMixed) {
         pair_mixed(I.x[q], I.y[q], I.z[q], I.vx[q], I.vy[q], I.vz[q], xjq, yj, zj, vxj, vyj, vzj,
-                   self ? 0.0 : mj, kMaskSelf ? eps2 : I.e2[q], I.Af[q]);
+                   self ? 0.0 : mj, kMaskSelf ? eps2 : I.e2[q], I.A[q], I.Af[q]);
       } else {
         pair_fp64(I.x[q], I.y[q], I.z[q], I.vx[q], I.vy[q], I.vz[q], xjq, yj, zj, vxj, vyj, vzj,
                   self ? 0.0 : mj, kMaskSelf ? eps2 : I.e2[q], I.A[q]);
@@ -390,15 +391,12 @@ __device__ __forceinline__ void tile_pairs(const double (*sj)[kTileJ], int cnt, 
   for (int kk = 0; kk < full; kk += LJ) pairs_with(kk + jsub);
   if (full + jsub < cnt) pairs_with(full + jsub);
   if (kMixed) {
-    // At most kTileJ / LJ terms per lane in FP32, then into FP64.
+    // At most kTileJ / LJ acceleration terms per lane in FP32, then into FP64.
 #pragma unroll
     for (int q = 0; q < kI; ++q) {
       I.A[q].ax += (double)I.Af[q].ax;
       I.A[q].ay += (double)I.Af[q].ay;
       I.A[q].az += (double)I.Af[q].az;
-      I.A[q].jx += (double)I.Af[q].jx;
-      I.A[q].jy += (double)I.Af[q].jy;
-      I.A[q].jz += (double)I.Af[q].jz;
     }
   }
 }

@@ -1,5 +1,6 @@
-"""Mixed-precision pair arithmetic (GD_FLAG_MIXED): FP64 differences, FP32
-pair terms, FP32 tile sums folded into FP64. Tolerance: max relative error
+"""Mixed-precision pair arithmetic (GD_FLAG_MIXED): FP64 differences and
+scalar factors, FP32 acceleration terms with FP32 tile sums folded into
+FP64, FP64 jerk terms. Tolerance: max relative error
 2e-6 per particle on acceleration and on jerk against the oracle's
 compensated FP64 sums (and the mode must differ from FP64, showing it runs).
 Energy drift of an integration stays below 1e-6 per time unit. Pools in
@@ -46,18 +47,41 @@ def test_mixed_initial_force_plummer(n, seed):
     assert np.abs(a - a64).max() > 0.0
 
 
-def test_mixed_imf_n262144_sampled():
+def _kappa(m, x, v, eps, i):
+    """Conditioning of particle i's sums: sum over j of |pair term| over
+    |sum|, for the acceleration and for the jerk (Euclidean norms)."""
+    r = x - x[i]
+    w = v - v[i]
+    s = (r * r).sum(1) + eps * eps
+    q = 1.0 / np.sqrt(s)
+    mq3 = m * q ** 3
+    mq3[i] = 0.0
+    ta = mq3[:, None] * r
+    tj = mq3[:, None] * (w - 3.0 * ((r * w).sum(1) * q * q)[:, None] * r)
+    ka = np.linalg.norm(ta, axis=1).sum() / np.linalg.norm(ta.sum(0))
+    kj = np.linalg.norm(tj, axis=1).sum() / np.linalg.norm(tj.sum(0))
+    return ka, kj
+
+
+def test_mixed_imf_n262144_against_oracle():
     """The mixed-precision workload: N = 262144, power-law IMF (slope -2.35
-    on [0.1, 100], total mass 1), eps 1e-4; 160 sampled particles including
-    the 32 innermost."""
+    on [0.1, 100], total mass 1), eps 1e-4. 4096 random particles, the 32
+    innermost, and the 64 rows where the mixed forces differ most from the
+    FP64 path's (acceleration and jerk each) against the oracle's
+    compensated sums: at most 2e-6 on every row."""
     n = 262144
     m, x, v = plummer_imf(n, 5)
     a, j = _initial(m, x, v, MIXED)
-    idx = _sample(n, x, 128, seed=1)
+    a64, j64 = _initial(m, x, v, 0)
+    worst = np.concatenate([np.argsort(rel_err_rows(a, a64))[-64:], np.argsort(rel_err_rows(j, j64))[-64:]])
+    idx = np.unique(np.concatenate([_sample(n, x, 4096, seed=1), worst]))
     ra, rj = oracle.force(m, x, v, 1e-4, idx=idx, compensated=True, threads=oracle.max_threads())
-    ea, ej = rel_err_rows(a[idx], ra).max(), rel_err_rows(j[idx], rj).max()
-    print(f"IMF N=262144: mixed max rel err acc {ea:.2e} jerk {ej:.2e}")
-    assert ea <= MIX_TOL and ej <= MIX_TOL
+    ea, ej = rel_err_rows(a[idx], ra), rel_err_rows(j[idx], rj)
+    print(f"IMF N=262144, {len(idx)} rows: mixed max rel err acc {ea.max():.2e} jerk {ej.max():.2e}")
+    for k in np.argsort(np.maximum(ea, ej))[-3:]:
+        ka, kj = _kappa(m, x, v, 1e-4, idx[k])
+        print(f"  row {idx[k]}: acc {ea[k]:.2e} (kappa {ka:.1e}), jerk {ej[k]:.2e} (kappa {kj:.1e})")
+    assert ea.max() <= MIX_TOL and ej.max() <= MIX_TOL
 
 
 def test_mixed_unsoftened_and_central_particle():
@@ -113,10 +137,7 @@ def test_mixed_pool_equals_mixed_context_bitwise():
 
 def test_mixed_against_fp64_all_particles():
     """All N = 16384 particles, mixed against the FP64 path on the same state:
-    the acceleration within 2e-6 everywhere; the jerk within 2e-6 for at
-    least 99.9 % of particles (its outliers are particles whose jerk sum
-    cancels strongly, which FP32 pair terms cannot follow: 1e-5 is the
-    bound asserted for them)."""
+    acceleration and jerk within 2e-6 on every particle."""
     n = 16384
     m, x, v = plummer(n, 1)
     idx = torch.arange(n, dtype=torch.int32, device=DEV)
@@ -131,10 +152,9 @@ def test_mixed_against_fp64_all_particles():
         cl.close()
     ea = rel_err_rows(out[MIXED][0], out[0][0])
     ej = rel_err_rows(out[MIXED][1], out[0][1])
-    print(f"all particles: acc max {ea.max():.2e}; jerk p99.9 {np.percentile(ej, 99.9):.2e} max {ej.max():.2e}")
+    print(f"all particles: acc max {ea.max():.2e}; jerk max {ej.max():.2e}")
     assert ea.max() <= MIX_TOL
-    assert np.percentile(ej, 99.9) <= MIX_TOL
-    assert ej.max() <= 1e-5
+    assert ej.max() <= MIX_TOL
 
 
 def test_mixed_replays_fp64_block_steps_imf():
@@ -142,8 +162,8 @@ def test_mixed_replays_fp64_block_steps_imf():
     an FP64 run: before each of the first 256 block steps the mixed context
     takes the FP64 context's state, so both predict the same j stream and
     select the same active block; the mixed force of that block is then
-    compared with the FP64 one, row by row, with the bounds used for all
-    particles at t = 0."""
+    compared with the FP64 one, row by row: acceleration and jerk within
+    2e-6 on every row."""
     n = 262144
     m, x, v = plummer_imf(n, 5)
     ctx = {0: g.Cluster(m, x, v, device=DEV), MIXED: g.Cluster(m, x, v, device=DEV, flags=MIXED)}
@@ -170,9 +190,8 @@ def test_mixed_replays_fp64_block_steps_imf():
     for cl in ctx.values():
         cl.close()
     ea, ej = np.concatenate(ea), np.concatenate(ej)
-    print(f"256 replayed steps, {len(ea)} rows (N_act {min(sizes)}..{max(sizes)}): acc max {ea.max():.2e}; "
-          f"jerk p99.9 {np.percentile(ej, 99.9):.2e} max {ej.max():.2e}")
+    print(f"256 replayed steps, {len(ea)} rows (N_act {min(sizes)}..{max(sizes)}): acc max {ea.max():.2e} "
+          f"(p99.9 {np.percentile(ea, 99.9):.2e}); jerk max {ej.max():.2e}")
     assert min(sizes) < max(sizes)
     assert ea.max() <= MIX_TOL
-    assert np.percentile(ej, 99.9) <= MIX_TOL
-    assert ej.max() <= 1e-5
+    assert ej.max() <= MIX_TOL
