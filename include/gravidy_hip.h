@@ -67,16 +67,17 @@ typedef struct {
 
 /* gd_params.flags: mixed-precision pair arithmetic (the alternative to FP64
  * that Sec. 2.3 names) in every force evaluation of the context or pool
- * (initial force, block steps, gd_force). Per pair,
- * the scalar factors (differences, r.r + eps^2, r.w, the inverse square
- * root, m q^3 and 3 (r.w) q^2) are FP64; the vector terms of Eq. (3) and of
- * its time derivative are formed in FP32 from the differences rounded to
- * FP32, and their sums over each j tile (at most 256 / LJ terms per lane)
- * are FP32 before they are added into FP64 accumulators. The pair with a
- * central particle, the predictor, the corrector, the time steps, the
- * schedule and the energy stay FP64. Force and jerk then differ from the
- * FP64 path by a relative error of order 1e-7 to 1e-6 (at most 2e-6 on the
- * tested workloads). */
+ * (initial force, block steps, gd_force). Per pair, the scalar factors
+ * (differences, r.r + eps^2, r.w, the inverse square root, m q^3 and
+ * 3 (r.w) q^2) are FP64. The acceleration terms of Eq. (3) are formed in FP32
+ * from m q^3 and the differences rounded to FP32, and summed in FP32 over
+ * each j tile (at most 256 / LJ terms per lane) before they are added into
+ * FP64 accumulators. The jerk terms stay FP64: jerk sums that cancel strongly
+ * defeat FP32 terms. The pair with a central particle, the predictor, the
+ * corrector, the time steps, the schedule and the energy stay FP64. The
+ * acceleration then differs from the FP64 path's by a relative error of
+ * order 1e-7 (at most 1.7e-6 on the tested workloads), the jerk by rounding
+ * (about 1e-13). */
 #define GD_FLAG_MIXED 1
 
 typedef struct {
@@ -127,8 +128,9 @@ gd_status gd_reinit(gd_ctx* c, const double* m, const double* x, const double* v
 /*
  * Force-kernel timing. With enable != 0, gd_step_to runs its block steps as
  * direct launches on the context's stream instead of graph replays, and
- * every force launch issued by gd_reinit and gd_step_to records its own
- * start and end in HIP events (hipExtLaunchKernelGGL); the elapsed times of
+ * every force launch issued by gd_reinit, gd_step_to and gd_force with an
+ * index list records its own start and end in HIP events
+ * (hipExtLaunchKernelGGL); the elapsed times of
  * the launches that did work are summed. Counters restart at zero on every
  * call. gd_profile_get reports the summed milliseconds, the number of such
  * launches, and their pair interactions (N_act * N each). Host outputs; any

@@ -505,10 +505,25 @@ gd_status gd_force(gd_ctx* c, const int32_t* idx, int64_t n_act, double* acc, do
     GD_TRY(c->hip(launch_set_active(c->d, c->c, idx, (int)n_act, c->stream), "set active"));
     c->phase = kForcedExplicit;
   }
-  GD_TRY(c->hip(launch_force(c->d, c->c, c->stream), "force kernel"));
+  // With timing on, an explicit list's launch records its own start and end.
+  const bool timed = c->prof && idx != nullptr;
+  GD_TRY(c->hip(launch_force(c->d, c->c, c->stream, timed ? c->ev_s[kGraphSteps] : nullptr,
+                             timed ? c->ev_e[kGraphSteps] : nullptr),
+                "force kernel"));
   if (acc || jerk) GD_TRY(c->hip(launch_reduce_out(c->d, c->c, acc, jerk, c->stream), "force output"));
   if (idx != nullptr) {
     GD_TRY(read_sched(c));
+    if (timed) {
+      float ms = 0.f;
+      GD_TRY(c->hip(hipEventElapsedTime(&ms, c->ev_s[kGraphSteps], c->ev_e[kGraphSteps]), "event time"));
+      c->prof_ms += ms;
+      c->prof_launches += 1;
+      c->prof_pairs += n_act * c->n;
+      const int b = prof_bucket(n_act);
+      c->bucket_ms[b] += ms;
+      c->bucket_launches[b] += 1;
+      c->bucket_pairs[b] += n_act * c->n;
+    }
     if (c->h_sc->bad_input) {
       c->h_sc->bad_input = 0;
       GD_TRY(c->hip(hipMemcpyAsync(&c->d.sc->bad_input, &c->h_sc->bad_input, sizeof(int),
