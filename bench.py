@@ -203,6 +203,10 @@ def main():
     ap.add_argument("--rho", type=float, default=1.0,
                     help="serving: arrival rate as a multiple of the sequential solve rate")
     ap.add_argument("--max-clusters", type=int, default=64, help="serving: pool slots")
+    ap.add_argument("--plan-sweep", action="store_true",
+                    help="time the force kernel of the workload's sphere for a range of block sizes, with "
+                         "gd_force's own decomposition and with every forced one (gd_force_plan); one JSON "
+                         "line per block size")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default=None,
                     help="serving and central-particle workloads: pair arithmetic (default: fp64 for "
                          "serving, mixed for the central-particle workload)")
@@ -233,6 +237,9 @@ def main():
     from paper_1702_00440_amd import gravidy as g
     from synth_inputs import WORKLOADS, plummer
 
+    if args.plan_sweep:
+        plan_sweep(args)
+        return
     if args.workload == "serving":
         serving_bench(args)
         return
@@ -363,6 +370,64 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+PLAN_SWEEP_SIZES = [1, 4, 16, 64, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048, 2560, 3072, 4096, 5000,
+                    6144, 8192, 12288, 16384]
+
+
+def plan_sweep(args):
+    """Force-kernel time per launch against the decomposition: for each
+    block size (lists of distinct random particles of the workload's sphere,
+    on its initial state), gd_force's own decomposition and every forced
+    one (16, 32 or 64 lanes per i; every slice count that gives a distinct
+    decomposition), each timed over several launches with HIP events."""
+    import numpy as np
+    import torch
+
+    from paper_1702_00440_amd import gravidy as g
+    from synth_inputs import WORKLOADS, plummer
+
+    w = WORKLOADS[args.workload]
+    n = w["n"]
+    m, x, v = plummer(n, w["seed"])
+    cl = g.Cluster(m, x, v, eta=w["eta"], eps=w["eps"], dt_max=w["dt_max"], dt_min=w["dt_min"],
+                   device="cuda:0")
+    g.gd_predict(cl.ctx, 0.0)
+    perm = np.random.default_rng(0).permutation(n).astype(np.int32)
+    tiles = (n + 255) // 256
+    slice_counts = sorted({-(-tiles // (-(-tiles // s))) for s in range(1, tiles + 1)})
+
+    def timed(run, n_act):
+        for _ in range(2):
+            run()
+        g.gd_profile_force(cl.ctx, True)
+        reps = max(4, min(100, int(1e9 / (n_act * n))))
+        for _ in range(reps):
+            run()
+        p = g.gd_profile_get(cl.ctx)
+        g.gd_profile_force(cl.ctx, False)
+        return p["force_ms"] * 1e3 / p["launches"]
+
+    for n_act in [a for a in PLAN_SWEEP_SIZES if a <= n]:
+        idx = torch.as_tensor(np.sort(perm[:n_act])).to("cuda:0")
+        auto = timed(lambda: g.gd_force(cl.ctx, idx), n_act)
+        forced = []
+        for lanes in (16, 32, 64):
+            for s in slice_counts:
+                try:
+                    g.gd_force_plan(cl.ctx, idx, lanes, s)
+                except g.GdError as e:  # more partial sums than the workspace holds
+                    if e.status != g.GD_EINVAL:
+                        raise
+                    continue
+                us = timed(lambda: g.gd_force_plan(cl.ctx, idx, lanes, s), n_act)
+                forced.append({"lanes_per_i": lanes, "slices": s, "us": us})
+        best = min(forced, key=lambda r: r["us"])
+        frac = lambda us: FLOPS_PER_PAIR * n_act * n / (us * 1e-6) / 1e12 / PEAK_FP64_VECTOR_TFLOPS
+        print(json.dumps({"n": n, "n_act": n_act, "auto_us": auto, "auto_frac": frac(auto), "best": best,
+                          "best_frac": frac(best["us"]), "forced": forced}), flush=True)
+    cl.close()
 
 
 def _rel_rows(a, b):

@@ -183,6 +183,23 @@ gd_status gd_predict(gd_ctx* c, const double* t);
 gd_status gd_force(gd_ctx* c, const int32_t* idx, int64_t n_act, double* acc, double* jerk);
 
 /*
+ * gd_force for an index list with a chosen decomposition of the force kernel
+ * (its split of the j sum; Sec. 2.5 describes the paper's): lanes_per_i lanes
+ * of a wave share each listed particle (16, 32 or 64), and the n particles
+ * are cut into at most `slices` j slices of whole 256-particle tiles (as many
+ * as keep each slice's tile count, none empty), whose partial sums are then
+ * added in slice order. Every decomposition sums the same terms in another
+ * order, so results agree to rounding; gd_force picks one from n_act and n.
+ * For tests of every kernel variant and for timing them (with
+ * gd_profile_force). Arguments and errors as gd_force with idx != NULL, plus
+ * GD_EINVAL for lanes_per_i outside {16, 32, 64}, slices outside
+ * [1, ceil(n / 256)], or a decomposition whose partial sums (slices times
+ * n_act) exceed the workspace's partial-force buffer. Synchronises.
+ */
+gd_status gd_force_plan(gd_ctx* c, const int32_t* idx, int64_t n_act, int32_t lanes_per_i, int32_t slices,
+                        double* acc, double* jerk);
+
+/*
  * Active set of the last gd_predict(NULL): writes N_act device int32 indices
  * to idx (capacity n; may be NULL) and N_act to *n_act (host). Synchronises.
  * The order of the list is unspecified; results never depend on it.

@@ -489,8 +489,14 @@ gd_status gd_predict(gd_ctx* c, const double* t) {
   return GD_OK;
 }
 
-gd_status gd_force(gd_ctx* c, const int32_t* idx, int64_t n_act, double* acc, double* jerk) {
-  if (!c) return GD_EINVAL;
+}  // extern "C"
+
+namespace {
+
+// The force of the current active set (idx == NULL) or of an index list,
+// with make_plan's decomposition (forced_lj == 0) or a forced one.
+gd_status force_of(gd_ctx* c, const int32_t* idx, int64_t n_act, double* acc, double* jerk, int forced_lj,
+                   int forced_s) {
   if (c->phase == kIdle) return c->fail(GD_ESTATE, "gd_force before gd_predict");
   if (idx == nullptr) {
     if (c->phase != kPredictedAuto && c->phase != kForcedAuto)
@@ -502,7 +508,7 @@ gd_status gd_force(gd_ctx* c, const int32_t* idx, int64_t n_act, double* acc, do
       c->phase = kForcedExplicit;
       return GD_OK;
     }
-    GD_TRY(c->hip(launch_set_active(c->d, c->c, idx, (int)n_act, c->stream), "set active"));
+    GD_TRY(c->hip(launch_set_active(c->d, c->c, idx, (int)n_act, c->stream, forced_lj, forced_s), "set active"));
     c->phase = kForcedExplicit;
   }
   // With timing on, an explicit list's launch records its own start and end.
@@ -534,6 +540,31 @@ gd_status gd_force(gd_ctx* c, const int32_t* idx, int64_t n_act, double* acc, do
     }
   }
   return GD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gd_status gd_force(gd_ctx* c, const int32_t* idx, int64_t n_act, double* acc, double* jerk) {
+  if (!c) return GD_EINVAL;
+  return force_of(c, idx, n_act, acc, jerk, 0, 0);
+}
+
+gd_status gd_force_plan(gd_ctx* c, const int32_t* idx, int64_t n_act, int32_t lanes_per_i, int32_t slices,
+                        double* acc, double* jerk) {
+  if (!c) return GD_EINVAL;
+  if (!idx) return c->fail(GD_EINVAL, "gd_force_plan needs an index list");
+  const int lj = lanes_per_i == 16 ? 4 : lanes_per_i == 32 ? 5 : lanes_per_i == 64 ? 6 : 0;
+  if (lj == 0) return c->fail(GD_EINVAL, "lanes_per_i must be 16, 32 or 64");
+  const long long tiles = (c->n + kTileJ - 1) / kTileJ;
+  if (slices < 1 || slices > tiles) return c->fail(GD_EINVAL, "slices must be in [1, ceil(n / 256)]");
+  if (n_act < 0 || n_act > c->n) return c->fail(GD_EINVAL, "n_act out of range");
+  const Plan p = plan_with((int)n_act, (int)c->n, lj, slices, ipl_of(c->c));
+  if ((long long)p.s * n_act > c->c.part_cs)
+    return c->fail(GD_EINVAL, "%d slices of %lld particles exceed the partial-force buffer", p.s,
+                   (long long)n_act);
+  return force_of(c, idx, n_act, acc, jerk, lj, slices);
 }
 
 gd_status gd_active(gd_ctx* c, int32_t* idx, int64_t* n_act) {

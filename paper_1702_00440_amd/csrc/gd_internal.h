@@ -19,14 +19,17 @@ constexpr int kTileJ = 256;
 constexpr int kIPerLane = 2;
 constexpr int kIPerLaneLarge = 4;
 constexpr int kLargeN = 131072;
-// Work items the force decomposition aims for (about 4 workgroups per CU).
-constexpr int kTargetItems = 1024;
+// Items the force decomposition aims for: slices are added (in powers of
+// two) while i tiles times slices stays within kSliceItems, about two items
+// per workgroup of the grid.
+constexpr int kSliceItems = 2048;
+// Fewest work units (i tiles times j tiles, times the i per lane) at which
+// the decomposition stops widening the lanes per i.
+constexpr int kMinUnits = 1536;
 // Upper bound of the force grid: workgroups loop over items beyond it.
 constexpr int kForceGrid = 1024;
 // Upper bound of the corrector grid.
 constexpr int kCorrectGrid = 2048;
-// A lane of the split-j layout keeps at least this many j per slice.
-constexpr int kMinJPerLane = 4;
 // Shortest j slice (one LDS tile): it bounds the number of slice partials a
 // particle has (N / kMinSlice). Small blocks shorten each lane's serial
 // chain of pair evaluations with more lanes per i instead (LJ up to 64).
@@ -84,33 +87,43 @@ struct Sched {
 // The plan depends only on (n_act, n). The kernel that fixes n_act for a
 // step (predictor, or the explicit index list) stores it in the Sched record,
 // and the force kernel and every slice reduction read that one copy.
-// The decomposition with LJ = 2^lj lanes per i and ipl i per lane; *stop
-// tells whether make_plan takes it (enough items, or the last candidate).
-__host__ __device__ inline Plan plan_for_lj(int n_act, int n, int lj, int ipl, bool* stop) {
-  int max_s = (n + kMinSlice - 1) / kMinSlice;
-  if (max_s < 1) max_s = 1;
-  const int it = (kBlock >> lj) * ipl;
-  int nit = (n_act + it - 1) / it;
-  if (nit < 1) nit = 1;
-  int s = kTargetItems / nit;
-  if (s >= 8) s &= ~7;  // slice index then follows blockIdx % 8, i.e. the XCD
-  if (s > max_s) s = max_s;
-  if (s < 1) s = 1;
-  const int len = (n + s - 1) / s;
-  const bool enough = nit * s >= kTargetItems;
-  const bool last = lj == 6 || (len >> (lj + 1)) < kMinJPerLane;
-  *stop = enough || last;
+// The decomposition with LJ = 2^lj lanes per i, ipl i per lane and at most
+// s_req slices of whole LDS tiles (as many as keep each slice's tile count,
+// with none empty).
+__host__ __device__ inline Plan plan_with(int n_act, int n, int lj, int s_req, int ipl) {
+  int tiles = (n + kTileJ - 1) / kTileJ;
+  if (tiles < 1) tiles = 1;
+  const int s0 = s_req < 1 ? 1 : (s_req > tiles ? tiles : s_req);
+  const int tps = (tiles + s0 - 1) / s0;  // tiles per slice
   Plan p;
   p.lj = lj;
-  p.it = it;
-  p.nit = nit;
-  p.s = s;
-  p.len = len;
-  p.items = nit * s;
+  p.it = (kBlock >> lj) * ipl;
+  p.nit = (n_act + p.it - 1) / p.it;
+  if (p.nit < 1) p.nit = 1;
+  p.s = (tiles + tps - 1) / tps;
+  p.len = tps * kTileJ;
+  p.items = p.nit * p.s;
   return p;
 }
 
-// The first lj from kMinLj up that gives enough items (or the last one).
+// The decomposition make_plan considers at lj: slice count the largest power
+// of two (at most one per tile) for which i tiles times slices stays within
+// kSliceItems. *stop tells whether make_plan takes it: enough work units for
+// the grid at this lj with i tiles at least half full, or the last
+// candidate (LJ = 64).
+__host__ __device__ inline Plan plan_for_lj(int n_act, int n, int lj, int ipl, bool* stop) {
+  int tiles = (n + kTileJ - 1) / kTileJ;
+  if (tiles < 1) tiles = 1;
+  const int it = (kBlock >> lj) * ipl;
+  int nit = (n_act + it - 1) / it;
+  if (nit < 1) nit = 1;
+  int s = 1;
+  while (2 * s <= tiles && 2 * s * nit <= kSliceItems) s *= 2;
+  *stop = lj == 6 || ((long long)nit * tiles * ipl >= kMinUnits && 2 * n_act >= nit * it);
+  return plan_with(n_act, n, lj, s, ipl);
+}
+
+// The first lj from kMinLj up that gives enough work units (or the last one).
 __host__ __device__ inline Plan make_plan(int n_act, int n, int ipl) {
   for (int lj = kMinLj;; ++lj) {
     bool stop = false;
@@ -121,12 +134,12 @@ __host__ __device__ inline Plan make_plan(int n_act, int n, int ipl) {
 
 // Rows of the partial-force buffer a context of n particles with ipl i per
 // lane needs: for every plan, s * n_act <= s * nit * it <= max(nit,
-// kTargetItems) * it with it <= (kBlock >> kMinLj) * ipl, and
+// kSliceItems) * it with it <= (kBlock >> kMinLj) * ipl, and
 // s * n_act <= (n / kMinSlice rounded up) * n. More i per lane never needs
 // fewer rows.
 constexpr long long partial_rows(long long n, int ipl) {
   const long long it_max = (long long)(kBlock >> kMinLj) * ipl;
-  const long long by_items = n + it_max + (long long)kTargetItems * it_max;
+  const long long by_items = n + it_max + (long long)kSliceItems * it_max;
   const long long by_slices = ((n + kMinSlice - 1) / kMinSlice) * n;
   const long long rows = by_items < by_slices ? by_items : by_slices;
   // Also scratch of the diagnostics sort: 1.5 * 2n + n / 64 + 8 doubles.
@@ -269,7 +282,10 @@ hipError_t launch_reduce_out(const Dev& d, const Consts& c, double* acc, double*
 hipError_t launch_energy(const Dev& d, const Consts& c, int unsoft, hipStream_t s);
 hipError_t launch_set_tend(const Dev& d, long long t_end, hipStream_t s);
 hipError_t launch_reset_sched(const Dev& d, long long t_now, hipStream_t s);
-hipError_t launch_set_active(const Dev& d, const Consts& c, const int32_t* idx, int n_act, hipStream_t s);
+// forced_lj > 0: the decomposition plan_with(n_act, n, forced_lj, forced_s)
+// instead of make_plan's.
+hipError_t launch_set_active(const Dev& d, const Consts& c, const int32_t* idx, int n_act, hipStream_t s,
+                             int forced_lj = 0, int forced_s = 0);
 hipError_t launch_copy_active(const Dev& d, const Consts& c, int32_t* idx, hipStream_t s);
 hipError_t launch_get_state(const Dev& d, const Consts& c, double* x, double* v, double* a,
                             double* jerk, double* t_i, double* dt_i, hipStream_t s);

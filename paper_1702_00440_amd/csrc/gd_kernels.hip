@@ -561,7 +561,10 @@ __device__ __forceinline__ void force_body(const Dev& d, const Consts& c, int bl
   // decomposition loads its items afresh.
   const bool spec = blk < c.s1;
   if (spec) {
-    const int len1 = (n + c.s1 - 1) / c.s1;
+    // Slices are whole tiles: s1 slices of ceil(tiles / s1) tiles each (the
+    // slice length of plan_with for that slice count).
+    const int tiles = (n + kTileJ - 1) / kTileJ;
+    const int len1 = ((tiles + c.s1 - 1) / c.s1) * kTileJ;
     const int j0 = blk * len1, j1 = min(n, j0 + len1);
     const int lj1 = lj1_of(c);
     load_i(0, (kBlock >> lj1) * kI, tid >> lj1, kBlock >> lj1, n - 1);
@@ -1270,8 +1273,8 @@ __global__ void k_set_tend(Sched* __restrict__ sc, long long t_end) {
 }
 
 // Explicit active list for gd_force(idx, ...): range-checked copy.
-__global__ void k_set_active(Sched* __restrict__ sc, int n, int ipl, const int32_t* __restrict__ idx,
-                             int n_act, int* __restrict__ active, const double* __restrict__ px,
+__global__ void k_set_active(Sched* __restrict__ sc, int n, int ipl, int forced_lj, int forced_s,
+                             const int32_t* __restrict__ idx, int n_act, int* __restrict__ active, const double* __restrict__ px,
                              const double* __restrict__ py, const double* __restrict__ pz,
                              const double* __restrict__ pvx, const double* __restrict__ pvy,
                              const double* __restrict__ pvz, double* __restrict__ ix,
@@ -1282,7 +1285,7 @@ __global__ void k_set_active(Sched* __restrict__ sc, int n, int ipl, const int32
   if (k == 0) {
     sc->n_act = n_act;
     sc->done = 0;
-    sc->plan = make_plan(n_act, n, ipl);
+    sc->plan = forced_lj > 0 ? plan_with(n_act, n, forced_lj, forced_s, ipl) : make_plan(n_act, n, ipl);
   }
   if (k >= n_act) return;
   int i = idx[k];
@@ -1701,9 +1704,9 @@ hipError_t launch_reset_sched(const Dev& d, long long t_now, hipStream_t s) {
 }
 
 hipError_t launch_set_active(const Dev& d, const Consts& c, const int32_t* idx, int n_act,
-                             hipStream_t s) {
+                             hipStream_t s, int forced_lj, int forced_s) {
   hipLaunchKernelGGL(k_set_active, dim3(grid_for(n_act > 0 ? n_act : 1)), dim3(kBlock), 0, s,
-                     d.sc, c.n, ipl_of(c), idx, n_act, d.active, d.px, d.py, d.pz, d.pvx, d.pvy, d.pvz, d.ix,
+                     d.sc, c.n, ipl_of(c), forced_lj, forced_s, idx, n_act, d.active, d.px, d.py, d.pz, d.pvx, d.pvy, d.pvz, d.ix,
                      d.iy, d.iz, d.ivx, d.ivy, d.ivz);
   return hipGetLastError();
 }

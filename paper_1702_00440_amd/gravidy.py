@@ -72,6 +72,8 @@ def library():
                                        C.POINTER(i64)]
     lib.gd_predict.argtypes = [_VP, C.POINTER(C.c_double)]
     lib.gd_force.argtypes = [_VP, _VP, i64, _VP, _VP]
+    lib.gd_force_plan.argtypes = [_VP, _VP, i64, C.c_int32, C.c_int32, _VP, _VP]
+    lib.gd_force_plan.restype = st
     lib.gd_active.argtypes = [_VP, _VP, C.POINTER(i64)]
     lib.gd_correct.argtypes = [_VP]
     lib.gd_step_to.argtypes = [_VP, C.c_double, C.POINTER(gd_stats)]
@@ -208,6 +210,15 @@ def gd_force(ctx, idx=None, acc=None, jerk=None) -> None:
     n_act = 0 if idx is None else idx.shape[0]
     _check(library().gd_force(ctx, _ptr(idx, torch.int32, None, "idx"), n_act,
                               _ptr(acc, torch.float64, None, "acc"), _ptr(jerk, torch.float64, None, "jerk")), ctx)
+
+
+def gd_force_plan(ctx, idx, lanes_per_i: int, slices: int, acc=None, jerk=None) -> None:
+    """gd_force of an index list with a chosen decomposition of the force
+    kernel (lanes per listed particle, j slices)."""
+    n_act = idx.shape[0]
+    _check(library().gd_force_plan(ctx, _ptr(idx, torch.int32, None, "idx"), n_act, int(lanes_per_i),
+                                   int(slices), _ptr(acc, torch.float64, None, "acc"),
+                                   _ptr(jerk, torch.float64, None, "jerk")), ctx)
 
 
 GD_NOALLOC_MAX_N = 65536

@@ -62,6 +62,53 @@ def test_force_active_subsets(n_act):
     cl.close()
 
 
+@pytest.mark.parametrize("eps,flags", [(EPS, 0), (0.0, 0), (EPS, g.GD_FLAG_MIXED)])
+def test_every_decomposition(eps, flags):
+    """Every decomposition of the force kernel (16, 32 or 64 lanes per i;
+    1 to 12 j slices of a 3001-particle sphere, 12 tiles with a ragged last
+    one) for lists of 1, 37, 500 and 3001 particles, through gd_force_plan,
+    against the oracle (FP64: 1e-12; mixed: 2e-6 on the acceleration and
+    1e-12 on the jerk, which stays FP64). gd_force's own choice is one of
+    them: its result equals one forced decomposition's bitwise."""
+    n = 3001
+    m, x, v = plummer(n, 9)
+    cl = g.Cluster(m, x, v, eta=ETA, eps=eps, device=DEV, flags=flags)
+    g.gd_predict(cl.ctx, 0.0)
+    a_tol = 2e-6 if flags else F_TOL
+    for n_act in (1, 37, 500, 3001):
+        idx = np.random.default_rng(n_act).permutation(n)[:n_act].astype(np.int32)
+        idx_t = dev(idx, torch.int32)
+        ra, rj = oracle.force(m, x, v, eps, idx=idx, compensated=True, threads=oracle.max_threads())
+        acc = torch.empty(n_act, 3, dtype=torch.float64, device=DEV)
+        jrk = torch.empty_like(acc)
+        g.gd_force(cl.ctx, idx_t, acc, jrk)
+        auto = host(acc), host(jrk)
+        matches = 0
+        for lanes in (16, 32, 64):
+            for slices in range(1, 13):
+                g.gd_force_plan(cl.ctx, idx_t, lanes, slices, acc, jrk)
+                a, j = host(acc), host(jrk)
+                assert rel_err_rows(a, ra).max() <= a_tol, (n_act, lanes, slices)
+                assert rel_err_rows(j, rj).max() <= F_TOL, (n_act, lanes, slices)
+                matches += np.array_equal(a, auto[0]) and np.array_equal(j, auto[1])
+        assert matches >= 1, n_act
+    cl.close()
+
+
+def test_force_plan_rejects_bad_decompositions():
+    n = 16384
+    m, x, v = plummer(n, 10)
+    cl = g.Cluster(m, x, v, eta=ETA, eps=EPS, device=DEV)
+    g.gd_predict(cl.ctx, 0.0)
+    idx = dev(np.arange(2000), torch.int32)
+    for lanes, slices in [(8, 4), (128, 4), (16, 0), (16, 65), (64, 64)]:
+        with pytest.raises(g.GdError) as e:
+            g.gd_force_plan(cl.ctx, idx, lanes, slices)
+        assert e.value.status == g.GD_EINVAL, (lanes, slices)
+    g.gd_force_plan(cl.ctx, idx, 16, 8)
+    cl.close()
+
+
 def test_force_on_predicted_state():
     """Prediction to an explicit time, then force: compared with the
     oracle's predictor (fed the GPU's own a and jerk) and force."""
