@@ -297,6 +297,7 @@ def main():
     elapsed = max(wall, gpu_ms / 1e3)
     step_ms = [marks[k].elapsed_time(marks[k + 1]) for k in range(len(marks) - 1)]
     hist = nact_histogram(g.gd_nact_histogram(ctx))
+    refills = g.gd_refills(ctx)  # of the last timed integration
     prof = {"force_ms": 0.0, "launches": 0, "pairs": 0}
     buckets = []
     if not args.no_profile:
@@ -348,6 +349,7 @@ def main():
         "particle_steps": stats["particle_steps"],
         "pairs_per_step": stats["pair_interactions"] + n * n,
         "n_act_histogram": hist,
+        "refill_steps": refills,
         "roofline": {
             "bound": "alu",
             "achieved": achieved,

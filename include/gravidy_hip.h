@@ -352,6 +352,19 @@ gd_status gd_stats_get(gd_ctx* c, gd_stats* st);
 #define GD_NACT_BINS 32
 gd_status gd_nact_histogram(gd_ctx* c, int64_t* counts);
 
+/*
+ * gd_step_to replays block steps of two kernels each: the force (with the
+ * active set of the step) and the corrector, which also predicts every
+ * particle to the next block time it expects (the next multiple of the
+ * current smallest step) and lists the particles active then. When a
+ * corrected particle's new step changes the smallest one, the expectation
+ * fails, and the next replayed step predicts and lists anew instead of
+ * stepping (a refill; results are the same either way). *refills (host)
+ * receives the number of such steps since gd_init, gd_reinit or
+ * gd_set_state. Synchronises. Errors: GD_EINVAL for NULL arguments; GD_EHIP.
+ */
+gd_status gd_refills(gd_ctx* c, int64_t* refills);
+
 /* Free the host-side context (not the workspace, which the caller owns). NULL is a no-op. */
 void gd_destroy(gd_ctx* c);
 

@@ -47,7 +47,7 @@ size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 // Byte offsets of every array in the workspace.
 struct Layout {
   size_t sc, m, jm, x[3], v[3], a[3], j[3], p[3], pv[3], tick, lev, active, ip[3], ipv[3], ia[3], ij[3], ilev,
-      part, ebuf, nact_log, total;
+      tag, part, ebuf, nact_log, total;
 };
 
 // i particles per lane of a context's force kernel (see kIPerLaneLarge).
@@ -77,12 +77,14 @@ Layout make_layout(long long n, int ipl) {
   for (int d = 0; d < 3; ++d) L.pv[d] = take(nd);
   L.tick = take(sizeof(long long) * (size_t)n);
   L.lev = take((size_t)n);
-  L.active = take(sizeof(int) * (size_t)n);
-  for (int d = 0; d < 3; ++d) L.ip[d] = take(nd);
-  for (int d = 0; d < 3; ++d) L.ipv[d] = take(nd);
-  for (int d = 0; d < 3; ++d) L.ia[d] = take(nd);
-  for (int d = 0; d < 3; ++d) L.ij[d] = take(nd);
-  L.ilev = take(sizeof(int) * (size_t)n);
+  // two active lists
+  L.active = take(2 * sizeof(int) * (size_t)n);
+  for (int d = 0; d < 3; ++d) L.ip[d] = take(2 * nd);
+  for (int d = 0; d < 3; ++d) L.ipv[d] = take(2 * nd);
+  for (int d = 0; d < 3; ++d) L.ia[d] = take(2 * nd);
+  for (int d = 0; d < 3; ++d) L.ij[d] = take(2 * nd);
+  L.ilev = take(2 * sizeof(int) * (size_t)n);
+  L.tag = take(2 * sizeof(long long) * (size_t)n);
   L.part = take(sizeof(double) * 6 * (size_t)partial_rows(n, ipl));
   // At least kEnergyGrid entries: the diagnostics reuse the buffer for their results.
   const long long eitems = std::max<long long>(make_eplan((int)n).items, kEnergyGrid);
@@ -127,6 +129,7 @@ Dev carve(void* workspace, const Layout& L) {
     *ijs[k] = (double*)(w + L.ij[k]);
   }
   d.ilev = (int*)(w + L.ilev);
+  d.tag = (long long*)(w + L.tag);
   d.part = (double*)(w + L.part);
   d.ebuf = (double*)(w + L.ebuf);
   d.nact_log = (int*)(w + L.nact_log);
@@ -265,12 +268,14 @@ gd_status energy_now(gd_ctx* c, int unsoft, double out[3]) {
   return GD_OK;
 }
 
-// One block step: predict (auto schedule), force, correct. With events
-// (direct launches only), the force launch records its own start and end.
-gd_status enqueue_step(gd_ctx* c, hipStream_t s, hipEvent_t ev_s, hipEvent_t ev_e) {
-  GD_TRY(c->hip(launch_predict(c->d, c->c, kPredAuto, 0.0, s), "predict kernel"));
-  GD_TRY(c->hip(launch_force(c->d, c->c, s, ev_s, ev_e), "force kernel"));
-  return c->hip(launch_correct(c->d, c->c, s), "correct kernel");
+// One block step of parity par: the force kernel (which finds the step from
+// the level histogram and checks the list and j stream the previous step's
+// corrector prepared) and the corrector (which also prepares the next step's).
+// With events (direct launches only), the force launch records its own start
+// and end.
+gd_status enqueue_step(gd_ctx* c, hipStream_t s, int par, hipEvent_t ev_s, hipEvent_t ev_e) {
+  GD_TRY(c->hip(launch_step_force(c->d, c->c, par, s, ev_s, ev_e), "force kernel"));
+  return c->hip(launch_step_correct(c->d, c->c, par, s), "correct kernel");
 }
 
 // Captures kGraphSteps block steps into *out.
@@ -295,7 +300,7 @@ gd_status build_graph(gd_ctx* c, int ring) {
                 "begin capture"));
   gd_status st = GD_OK;
   for (int k = 0; k < kGraphSteps && st == GD_OK; ++k)
-    st = enqueue_step(c, c->capture_stream, nullptr, nullptr);
+    st = enqueue_step(c, c->capture_stream, k & 1, nullptr, nullptr);
   if (st == GD_OK) {
     hipLaunchKernelGGL(k_status_out, dim3(1), dim3(64), 0, c->capture_stream,
                        (const unsigned long long*)c->d.sc, (unsigned long long*)c->h_ring[ring]);
@@ -649,10 +654,16 @@ gd_status gd_step_to(gd_ctx* c, double t_end, gd_stats* st) {
   c->phase = kIdle;
   GD_TRY(read_sched(c));
   long long steps_before = c->h_sc->block_steps, pairs_before = c->h_sc->pairs;
+  bool prepared = false;
   while (c->t_now < target) {
     // Advance to the next multiple of dt_max, where all particles meet.
     const long long chunk_end = (c->t_now / per_max + 1) * per_max;
     GD_TRY(c->hip(launch_set_tend(c->d, chunk_end, c->stream), "prepare"));
+    if (!prepared) {
+      // The list and j stream of the first step, for parity 0.
+      GD_TRY(c->hip(launch_prepare(c->d, c->c, c->stream), "prepare kernel"));
+      prepared = true;
+    }
     if (!c->prof) {
       GD_TRY(replay_chunk(c, chunk_end));
       c->t_now = c->h_sc->t_now;
@@ -665,7 +676,7 @@ gd_status gd_step_to(gd_ctx* c, double t_end, gd_stats* st) {
     // launch between its own events and each step's N_act logged.
     for (;;) {
       for (int k = 0; k < kGraphSteps; ++k) {
-        GD_TRY(enqueue_step(c, c->stream, c->ev_s[k], c->ev_e[k]));
+        GD_TRY(enqueue_step(c, c->stream, k & 1, c->ev_s[k], c->ev_e[k]));
         GD_TRY(c->hip(launch_log_nact(c->d, c->d.nact_log + k, c->stream), "log kernel"));
       }
       GD_TRY(c->hip(hipMemcpyAsync(c->h_nact, c->d.nact_log, sizeof(int) * kGraphSteps,
@@ -673,9 +684,12 @@ gd_status gd_step_to(gd_ctx* c, double t_end, gd_stats* st) {
                     "read log"));
       GD_TRY(read_sched(c));
       if (c->h_sc->nonfinite) return c->fail(GD_ENONFINITE, "non-finite acceleration or jerk");
-      // Steps run in order; the first (block_steps delta) of the batch were real.
+      // The steps that computed a force logged their N_act (the others, past
+      // the stop time or rebuilding their list, logged 0).
       const long long ran = c->h_sc->block_steps - steps_before;
-      for (long long k = 0; k < ran && k < kGraphSteps; ++k) {
+      long long timed = 0;
+      for (int k = 0; k < kGraphSteps; ++k) {
+        if (c->h_nact[k] <= 0) continue;
         float ms = 0.f;
         GD_TRY(c->hip(hipEventElapsedTime(&ms, c->ev_s[k], c->ev_e[k]), "event time"));
         c->prof_ms += ms;
@@ -683,7 +697,9 @@ gd_status gd_step_to(gd_ctx* c, double t_end, gd_stats* st) {
         c->bucket_ms[b] += ms;
         c->bucket_launches[b] += 1;
         c->bucket_pairs[b] += (long long)c->h_nact[k] * c->n;
+        ++timed;
       }
+      if (timed != ran) return c->fail(GD_EHIP, "force timing: %lld logged steps, %lld taken", timed, ran);
       c->prof_launches += ran;
       c->prof_pairs += c->h_sc->pairs - pairs_before;
       steps_before = c->h_sc->block_steps;
@@ -778,6 +794,14 @@ gd_status gd_nact_histogram(gd_ctx* c, int64_t* counts) {
   if (!counts) return c->fail(GD_EINVAL, "NULL argument");
   GD_TRY(read_sched(c));
   for (int b = 0; b < kNactBins; ++b) counts[b] = c->h_sc->nact_hist[b];
+  return GD_OK;
+}
+
+gd_status gd_refills(gd_ctx* c, int64_t* refills) {
+  if (!c) return GD_EINVAL;
+  if (!refills) return c->fail(GD_EINVAL, "NULL argument");
+  GD_TRY(read_sched(c));
+  *refills = c->h_sc->refills;
   return GD_OK;
 }
 

@@ -68,17 +68,30 @@ struct Plan {
 };
 
 // Device-resident scheduling and bookkeeping record (lives in the workspace).
+//
+// Block steps replayed from a graph run two kernels each (k_step_force,
+// k_step_correct), and the step's parity (0/1, a kernel argument) picks one of
+// two active lists: the corrector of a step predicts every particle to the
+// speculated next block time and builds the next step's list in the other
+// list, and the next force kernel checks the speculation (see k_step_force).
 struct Sched {
   long long t_now;   // current block time, in dt_min ticks
   long long t_next;  // block time of the step in flight
   long long t_end;   // steps whose t_next would exceed this are skipped
+  // The prepared list and j stream: (block time << 1) | list. One 64-bit word,
+  // so that a kernel that reads it while another workgroup rewrites it sees
+  // either the old pair or the new one.
+  long long spec;
   int n_act;         // active particles of the step in flight
   int kthr;          // a particle is active when its level >= kthr
   int done;          // 1: the step in flight is skipped (t_end reached)
-  int cnt;           // compaction counter of the active list
+  int lcnt[2];       // compaction counters of the two active lists
   int nonfinite;     // set when a non-finite force or jerk is seen
   int bad_input;     // set by input / state validation
+  int refill;        // 1: the step in flight rebuilt the list (no force, no correction)
+  int fine;          // finest occupied level of the step in flight
   long long block_steps, particle_steps, pairs, clamps;
+  long long refills;  // replayed steps that rebuilt their list instead of stepping
   long long nact_hist[kNactBins];  // block steps by floor(log2 N_act)
   Plan plan;                 // force decomposition of the step in flight
   int hist[kMaxLevels + 1];  // particles per level
@@ -177,10 +190,16 @@ struct Dev {
   double *px, *py, *pz, *pvx, *pvy, *pvz;  // predicted j stream
   long long* tick;                         // t_i in dt_min ticks
   unsigned char* lev;                      // dt_i = dt_max / 2^lev
-  int* active;                             // active list (positions 0..n_act-1)
-  double *ix, *iy, *iz, *ivx, *ivy, *ivz;  // predicted state of the active list, by position
-  double *iax, *iay, *iaz, *ijx, *ijy, *ijz;  // a, jerk at t_i of the active list, by position
-  int* ilev;                               // level of the active list, by position
+  // Two active lists, list q at offset q * n of each array (positions
+  // 0..n_act-1), with the listed particles' predicted state, a and jerk at
+  // t_i, and level, by position.
+  int* active;
+  double *ix, *iy, *iz, *ivx, *ivy, *ivz;
+  double *iax, *iay, *iaz, *ijx, *ijy, *ijz;
+  int* ilev;
+  // tag[q * n + j]: the block time for which particle j was put in list q
+  // (-1: never since the state was loaded).
+  long long* tag;
   double* part;                            // [6][partial_rows(n)]: position * s + slot
   double* ebuf;                            // energy partials [items][3] + result [3]
   int* nact_log;                           // force-timing pass: N_act of each timed step
@@ -275,7 +294,15 @@ hipError_t launch_predict(const Dev& d, const Consts& c, int mode, double t_expl
 hipError_t launch_force(const Dev& d, const Consts& c, hipStream_t s, hipEvent_t ev_start = nullptr,
                         hipEvent_t ev_stop = nullptr);
 hipError_t launch_correct(const Dev& d, const Consts& c, hipStream_t s);
-// Copies the N_act of the step in flight (0 if it was skipped) to *out.
+// The two kernels of a graph-replayed block step with parity par (see Sched).
+hipError_t launch_step_force(const Dev& d, const Consts& c, int par, hipStream_t s,
+                             hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+hipError_t launch_step_correct(const Dev& d, const Consts& c, int par, hipStream_t s);
+// Predicts every particle to the next block time and builds list 0 for it,
+// so that a step of parity 0 finds its list prepared.
+hipError_t launch_prepare(const Dev& d, const Consts& c, hipStream_t s);
+// Copies the N_act of the step in flight (0 if it was skipped or rebuilt its
+// list) to *out.
 hipError_t launch_log_nact(const Dev& d, int* out, hipStream_t s);
 hipError_t launch_init_dt(const Dev& d, const Consts& c, hipStream_t s);
 hipError_t launch_reduce_out(const Dev& d, const Consts& c, double* acc, double* jerk, hipStream_t s);

@@ -264,6 +264,7 @@ __device__ __forceinline__ void taylor6(double dt, double x0, double y0, double 
 struct NextStep {
   long long t_next;
   int kthr, n_act, done;
+  int fine;  // finest occupied level
 };
 
 // Sum over a wave of values in [0, 2^nbits), by bit slices: a ballot and a
@@ -300,6 +301,7 @@ __device__ __forceinline__ NextStep next_step_wave(int h, int lane, int kmax, lo
   r.kthr = max(0, kmax - tz);
   r.n_act = wave_sum_bits(lane >= r.kthr ? h : 0, nbits);
   r.done = r.t_next > t_end;
+  r.fine = kmx;
   return r;
 }
 
@@ -321,6 +323,105 @@ __device__ __forceinline__ Plan make_plan_wave(int n_act, int n, int ipl, int la
   q.len = __builtin_amdgcn_readlane(p.len, first);
   q.items = __builtin_amdgcn_readlane(p.items, first);
   return q;
+}
+
+// ---------------------------------------------------------------------------
+// Active lists and prediction to a block time (shared by the predictor, the
+// force kernel of a replayed step and its corrector)
+// ---------------------------------------------------------------------------
+
+// Positions in a list for the threads of the workgroup with take == true:
+// ranks by wave ballot, one atomic on the list's counter per workgroup. Every
+// thread of the workgroup must call it. The list order depends on which
+// workgroup's atomic lands first, but no result depends on the order: a
+// particle's force sums are the same at every list position.
+__device__ __forceinline__ int wg_append(bool take, int* counter) {
+  __shared__ int s_cnt[kBlock / 64];
+  __shared__ int s_base;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const unsigned long long ball = __ballot(take);
+  const int before = __popcll(ball & ((1ULL << lane) - 1ULL));
+  if (lane == 0) s_cnt[wave] = __popcll(ball);
+  __syncthreads();
+  if (tid == 0) {
+    int tot = 0;
+    for (int w = 0; w < kBlock / 64; ++w) {
+      const int cw = s_cnt[w];
+      s_cnt[w] = tot;
+      tot += cw;
+    }
+    s_base = tot ? atomicAdd(counter, tot) : 0;
+  }
+  __syncthreads();
+  const int pos = s_base + s_cnt[wave] + before;
+  __syncthreads();  // the shared words are reused by the next call
+  return pos;
+}
+
+// Entry pos of list q: particle j with its predicted state o, its a and jerk
+// at t_i and its level; and j's tag in list q (the block time of the step).
+__device__ __forceinline__ void list_store(const Dev& d, int n, int q, int pos, int j, const double (&o)[6],
+                                           double ax, double ay, double az, double jx, double jy, double jz,
+                                           int lv, long long tag) {
+  const size_t k = (size_t)q * n + pos;
+  d.active[k] = j;
+  d.ix[k] = o[0]; d.iy[k] = o[1]; d.iz[k] = o[2];
+  d.ivx[k] = o[3]; d.ivy[k] = o[4]; d.ivz[k] = o[5];
+  d.iax[k] = ax; d.iay[k] = ay; d.iaz[k] = az;
+  d.ijx[k] = jx; d.ijy[k] = jy; d.ijz[k] = jz;
+  d.ilev[k] = lv;
+  d.tag[(size_t)q * n + j] = tag;
+}
+
+// Stored state of one particle (corrected state, a and jerk at t_i, t_i, level).
+struct PState {
+  double x, y, z, vx, vy, vz, ax, ay, az, jx, jy, jz;
+  long long tick;
+  int lev;
+};
+
+__device__ __forceinline__ PState load_pstate(const Dev& d, int j) {
+  PState p;
+  p.x = d.x[j]; p.y = d.y[j]; p.z = d.z[j];
+  p.vx = d.vx[j]; p.vy = d.vy[j]; p.vz = d.vz[j];
+  p.ax = d.ax[j]; p.ay = d.ay[j]; p.az = d.az[j];
+  p.jx = d.jx[j]; p.jy = d.jy[j]; p.jz = d.jz[j];
+  p.tick = d.tick[j];
+  p.lev = d.lev[j];
+  return p;
+}
+
+// Particle j (valid) predicted over dt into the j stream (o receives the
+// predicted state).
+__device__ __forceinline__ void predict_store(const Dev& d, int j, double dt, const PState& p, double (&o)[6]) {
+  taylor6(dt, p.x, p.y, p.z, p.vx, p.vy, p.vz, p.ax, p.ay, p.az, p.jx, p.jy, p.jz, o);
+  d.px[j] = o[0]; d.py[j] = o[1]; d.pz[j] = o[2];
+  d.pvx[j] = o[3]; d.pvy[j] = o[4]; d.pvz[j] = o[5];
+}
+
+// The workgroup's particles [blk * kBlock, (blk + 1) * kBlock) predicted to
+// block time t (ticks) into the j stream; those with level >= kthr appended
+// to list q, tagged with t. p holds the thread's particle (loaded by the
+// caller, index min(j, n - 1)).
+__device__ __forceinline__ void predict_append(const Dev& d, const Consts& c, int blk, const PState& p,
+                                               long long t, int kthr, int q) {
+  const int j = blk * kBlock + threadIdx.x;
+  bool act = false;
+  double o[6];
+  if (j < c.n) {
+    predict_store(d, j, (double)(t - p.tick) * c.dt_min, p, o);
+    act = p.lev >= kthr;
+  }
+  const int pos = wg_append(act, &d.sc->lcnt[q]);
+  if (act) list_store(d, c.n, q, pos, j, o, p.ax, p.ay, p.az, p.jx, p.jy, p.jz, p.lev, t);
+}
+
+// The next block step from the Sched record, by one wave (next_step_wave):
+// every lane returns the same result.
+__device__ __forceinline__ NextStep schedule_wave(const Sched* __restrict__ sc, const Consts& c) {
+  const int lane = threadIdx.x & 63;
+  const int h = lane <= c.kmax ? sc->hist[lane] : 0;
+  return next_step_wave(h, lane, c.kmax, sc->t_now, sc->t_end, count_bits(c.n));
 }
 
 // ---------------------------------------------------------------------------
@@ -501,10 +602,14 @@ __device__ __forceinline__ void finish_item(const Dev& d, const Consts& c, int L
   }
 }
 
-template <bool kMaskSelf, bool kCentral, bool kMixed, int kI>
-__device__ __forceinline__ void force_body(const Dev& d, const Consts& c, int blk, int nblk) {
-  const Sched* __restrict__ sc = d.sc;
+// kStep: the force kernel of a graph-replayed block step (k_step_force), with
+// the active list of parity par; otherwise that of a step whose predictor ran
+// before (list 0).
+template <bool kMaskSelf, bool kCentral, bool kMixed, int kI, bool kStep = false>
+__device__ __forceinline__ void force_body(const Dev& d, const Consts& c, int blk, int nblk, int par = 0) {
+  Sched* __restrict__ sc = d.sc;
   const int n = c.n;
+  const size_t lo = (size_t)par * n;  // list offset
   const double* __restrict__ px = d.px;
   const double* __restrict__ py = d.py;
   const double* __restrict__ pz = d.pz;
@@ -527,7 +632,7 @@ __device__ __forceinline__ void force_body(const Dev& d, const Consts& c, int bl
 #pragma unroll
     for (int q = 0; q < kI; ++q) {
       I.pos[q] = itile * it + ilane + q * ilanes;
-      const int k = min(I.pos[q], kc);
+      const size_t k = lo + min(I.pos[q], kc);
       I.g[q] = (kMaskSelf || kCentral) ? d.active[k] : 0;
       // Softening enters only as the addend of r.r, so a per-i value costs
       // nothing: the central particle takes eps_bh for all of its pairs.
@@ -571,10 +676,55 @@ __device__ __forceinline__ void force_body(const Dev& d, const Consts& c, int bl
     if (j0 < j1) load_tile(j0, j1);
   }
 
-  if (sc->done) return;
-  const int n_act = sc->n_act;
-  if (n_act <= 0) return;
-  const Plan p = sc->plan;
+  int n_act;
+  Plan p;
+  if constexpr (kStep) {
+    // The step from the level histogram, in every wave (each wave gets the
+    // same result), then the check of the prepared list and j stream.
+    const NextStep nx = schedule_wave(sc, c);
+    const long long prepared = __hip_atomic_load(&sc->spec, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (nx.done) {
+      if (blk == 0 && tid == 0) {
+        sc->done = 1;
+        sc->refill = 0;
+      }
+      return;
+    }
+    if (prepared != ((nx.t_next << 1) | par)) {
+      // The corrector of the previous step predicted another block time, or
+      // prepared the other list: predict every particle to t_next and build
+      // list par ^ 1 instead of a force. The corrector then does nothing,
+      // and the next step (parity par ^ 1) finds its list prepared. A
+      // workgroup that reads the new record sees the other list as prepared
+      // and takes this path as well.
+      for (int b = blk; b < (n + kBlock - 1) / kBlock; b += nblk) {
+        const PState ps = load_pstate(d, min(b * kBlock + tid, n - 1));
+        predict_append(d, c, b, ps, nx.t_next, nx.kthr, par ^ 1);
+      }
+      if (blk == 0 && tid == 0) {
+        __hip_atomic_store(&sc->spec, (nx.t_next << 1) | (par ^ 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        sc->refill = 1;
+        sc->done = 0;
+      }
+      return;
+    }
+    n_act = nx.n_act;
+    p = make_plan_wave(n_act, n, ipl_of(c), tid & 63);
+    if (blk == 0 && tid == 0) {
+      sc->t_next = nx.t_next;
+      sc->kthr = nx.kthr;
+      sc->n_act = n_act;
+      sc->plan = p;
+      sc->fine = nx.fine;
+      sc->done = 0;
+      sc->refill = 0;
+    }
+  } else {
+    if (sc->done) return;
+    n_act = sc->n_act;
+    if (n_act <= 0) return;
+    p = sc->plan;
+  }
   if (blk >= p.items) return;
   // Same lanes per i and slices: same tile size, slice length and item map.
   const bool early = spec && p.lj == lj1_of(c) && p.s == c.s1;
@@ -615,6 +765,12 @@ __device__ __forceinline__ void force_body(const Dev& d, const Consts& c, int bl
 template <bool kMaskSelf, bool kCentral, bool kMixed, int kI>
 __global__ __launch_bounds__(kBlock) void k_force(Dev d, Consts c) {
   force_body<kMaskSelf, kCentral, kMixed, kI>(d, c, blockIdx.x, gridDim.x);
+}
+
+// The force kernel of a graph-replayed block step of parity par (see Sched).
+template <bool kMaskSelf, bool kCentral, bool kMixed, int kI>
+__global__ __launch_bounds__(kBlock) void k_step_force(Dev d, Consts c, int par) {
+  force_body<kMaskSelf, kCentral, kMixed, kI, true>(d, c, blockIdx.x, gridDim.x, par);
 }
 
 // ---------------------------------------------------------------------------
@@ -682,9 +838,18 @@ __device__ __forceinline__ bool finite6(const double f[6]) {
 // Everything the particle needs (slice partials, predicted state, a0, j0,
 // level) is read by list position in one memory round trip; L lanes per
 // particle share the slice reduction and the first lane corrects.
-__device__ __forceinline__ void correct_body(const Dev& d, const Consts& c, int blk, int nblk) {
+// kStep: the corrector of a graph-replayed block step of parity par, which
+// also predicts every corrected particle to the speculated next block time
+// (the next multiple of the finest step of this step: t_next + 2^(kmax -
+// fine)) into the j stream and appends those active then to list par ^ 1;
+// k_step_correct's other workgroups do the same for the particles this step
+// did not correct (predict_rest). Otherwise the corrector of a step whose
+// list is list 0.
+template <bool kStep>
+__device__ __forceinline__ void correct_body(const Dev& d, const Consts& c, int blk, int nblk, int par = 0) {
   Sched* __restrict__ sc = d.sc;
   const int tid = threadIdx.x;
+  const size_t lo = (size_t)par * c.n;  // list offset
   // Small blocks use the slice count of a one-particle block (s1, which n
   // alone fixes) and fill at most its first i tile. The workgroups that hold
   // those positions request their state, and their slice partials when one
@@ -704,12 +869,12 @@ __device__ __forceinline__ void correct_body(const Dev& d, const Consts& c, int 
     const int r1 = tid & (L1 - 1);
     const int kcap = (int)min((long long)c.n, c.part_cs / c.s1) - 1;
     const int k1 = min(blk * per1 + tid / L1, kcap);
-    i = d.active[k1];
-    lv = d.ilev[k1];
-    a0[0] = d.iax[k1]; a0[1] = d.iay[k1]; a0[2] = d.iaz[k1];
-    j0[0] = d.ijx[k1]; j0[1] = d.ijy[k1]; j0[2] = d.ijz[k1];
-    xp[0] = d.ix[k1]; xp[1] = d.iy[k1]; xp[2] = d.iz[k1];
-    vp[0] = d.ivx[k1]; vp[1] = d.ivy[k1]; vp[2] = d.ivz[k1];
+    i = d.active[lo + k1];
+    lv = d.ilev[lo + k1];
+    a0[0] = d.iax[lo + k1]; a0[1] = d.iay[lo + k1]; a0[2] = d.iaz[lo + k1];
+    j0[0] = d.ijx[lo + k1]; j0[1] = d.ijy[lo + k1]; j0[2] = d.ijz[lo + k1];
+    xp[0] = d.ix[lo + k1]; xp[1] = d.iy[lo + k1]; xp[2] = d.iz[lo + k1];
+    vp[0] = d.ivx[lo + k1]; vp[1] = d.ivy[lo + k1]; vp[2] = d.ivz[lo + k1];
     if (one_slot && r1 < c.s1) {
       const double* o = d.part + (size_t)k1 * c.s1 + r1;
 #pragma unroll
@@ -717,10 +882,24 @@ __device__ __forceinline__ void correct_body(const Dev& d, const Consts& c, int 
     }
   }
 
-  if (sc->done) return;
+  if constexpr (kStep) {
+    if (sc->done || sc->refill) {
+      // the list this step's corrector would have built next stays free
+      if (blk == 0 && tid == 0) {
+        sc->lcnt[par] = 0;
+        if (sc->refill) sc->refills += 1;
+      }
+      return;
+    }
+  } else {
+    if (sc->done) return;
+  }
   const int n_act = sc->n_act;
   const long long t_next = sc->t_next;
   const Plan p = sc->plan;
+  // speculated next block time (kStep)
+  const long long t_spec = kStep ? t_next + (1LL << (c.kmax - sc->fine)) : 0;
+  const int kthr_spec = kStep ? max(0, c.kmax - (int)__builtin_ctzll((unsigned long long)t_spec)) : 0;
   const int L = correct_lanes(p.s);
   const int per_wg = kBlock / L;
   if (blk * per_wg >= n_act && blk != 0) return;
@@ -735,7 +914,12 @@ __device__ __forceinline__ void correct_body(const Dev& d, const Consts& c, int 
     sc->pairs += (long long)n_act * c.n;
     if (n_act > 0) sc->nact_hist[31 - __clz(n_act)] += 1;
     sc->t_now = t_next;
-    sc->cnt = 0;
+    if (kStep) {
+      sc->lcnt[par] = 0;
+      sc->spec = (t_spec << 1) | (par ^ 1);
+    } else {
+      sc->lcnt[0] = 0;
+    }
   }
   const int r = tid & (L - 1);
   for (int base = blk * per_wg; base < n_act; base += nblk * per_wg) {
@@ -745,12 +929,12 @@ __device__ __forceinline__ void correct_body(const Dev& d, const Consts& c, int 
     const bool first = early && base == blk * per_wg;
     if (!first) {
       // Loads that do not depend on the reduction, issued with it.
-      i = d.active[kk];
-      lv = d.ilev[kk];
-      a0[0] = d.iax[kk]; a0[1] = d.iay[kk]; a0[2] = d.iaz[kk];
-      j0[0] = d.ijx[kk]; j0[1] = d.ijy[kk]; j0[2] = d.ijz[kk];
-      xp[0] = d.ix[kk]; xp[1] = d.iy[kk]; xp[2] = d.iz[kk];
-      vp[0] = d.ivx[kk]; vp[1] = d.ivy[kk]; vp[2] = d.ivz[kk];
+      i = d.active[lo + kk];
+      lv = d.ilev[lo + kk];
+      a0[0] = d.iax[lo + kk]; a0[1] = d.iay[lo + kk]; a0[2] = d.iaz[lo + kk];
+      j0[0] = d.ijx[lo + kk]; j0[1] = d.ijy[lo + kk]; j0[2] = d.ijz[lo + kk];
+      xp[0] = d.ix[lo + kk]; xp[1] = d.iy[lo + kk]; xp[2] = d.iz[lo + kk];
+      vp[0] = d.ivx[lo + kk]; vp[1] = d.ivy[lo + kk]; vp[2] = d.ivz[lo + kk];
     }
     double f[6];
     if (first && one_slot) {
@@ -761,60 +945,138 @@ __device__ __forceinline__ void correct_body(const Dev& d, const Consts& c, int 
     } else {
       reduce_slices(d.part, p.s, c.part_cs, k, L, r, valid, f);
     }
-    if (r != 0 || !valid) continue;
-    if (!finite6(f)) bk.bad = 1;
+    const bool owner = r == 0 && valid;  // the lane that corrects position k
+    bool take = false;
+    double o[6];
+    int nl = 0;
+    if (owner) {
+      if (!finite6(f)) bk.bad = 1;
 
-    // h and its powers are powers of two: dividing by h^2 and h^3 is the exact
-    // product with their reciprocals (from 1 / dt_min, scaled by 2^(lv - kmax)).
-    const double h = (double)(1LL << (c.kmax - lv)) * c.dt_min;
-    const double h2 = h * h, h3 = h2 * h;
-    const double ih = ldexp(c.inv_dt_min, lv - c.kmax);
-    const double ih2 = ih * ih, ih3 = ih2 * ih;
-    double a2[3], a3[3], a2e[3], xn[3], vn[3];
+      // h and its powers are powers of two: dividing by h^2 and h^3 is the exact
+      // product with their reciprocals (from 1 / dt_min, scaled by 2^(lv - kmax)).
+      const double h = (double)(1LL << (c.kmax - lv)) * c.dt_min;
+      const double h2 = h * h, h3 = h2 * h;
+      const double ih = ldexp(c.inv_dt_min, lv - c.kmax);
+      const double ih2 = ih * ih, ih3 = ih2 * ih;
+      double a2[3], a3[3], a2e[3], xn[3], vn[3];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      const double da = a0[q] - f[q];
-      a2[q] = (-6.0 * da - h * (4.0 * j0[q] + 2.0 * f[3 + q])) * ih2;
-      a3[q] = (12.0 * da + 6.0 * h * (j0[q] + f[3 + q])) * ih3;
-      xn[q] = xp[q] + a2[q] * (h2 * h2) / 24.0 + a3[q] * (h2 * h3) / 120.0;
-      vn[q] = vp[q] + a2[q] * h3 / 6.0 + a3[q] * (h2 * h2) / 24.0;
-      a2e[q] = a2[q] + h * a3[q];
+      for (int q = 0; q < 3; ++q) {
+        const double da = a0[q] - f[q];
+        a2[q] = (-6.0 * da - h * (4.0 * j0[q] + 2.0 * f[3 + q])) * ih2;
+        a3[q] = (12.0 * da + 6.0 * h * (j0[q] + f[3 + q])) * ih3;
+        xn[q] = xp[q] + a2[q] * (h2 * h2) / 24.0 + a3[q] * (h2 * h3) / 120.0;
+        vn[q] = vp[q] + a2[q] * h3 / 6.0 + a3[q] * (h2 * h2) / 24.0;
+        a2e[q] = a2[q] + h * a3[q];
+      }
+      const double na1 = norm3(f[0], f[1], f[2]);
+      const double nj1 = norm3(f[3], f[4], f[5]);
+      const double na2 = norm3(a2e[0], a2e[1], a2e[2]);
+      const double na3 = norm3(a3[0], a3[1], a3[2]);
+      const double dtstar = sqrt(c.eta * (na1 * na2 + nj1 * nj1) / (nj1 * na3 + na2 * na2));
+      const int kc = level_for(dtstar, c.dt_max, c.inv_dt_max, c.kmax);
+      if (kc >= lv) {
+        nl = kc;
+      } else if (lv >= 1 && (t_next & ((1LL << (c.kmax - lv + 1)) - 1)) == 0) {
+        nl = lv - 1;
+      } else {
+        nl = lv;
+      }
+      if (nl > c.kmax) {
+        nl = c.kmax;
+        atomicAdd(&bk.clamp, 1);
+      }
+      d.x[i] = xn[0]; d.y[i] = xn[1]; d.z[i] = xn[2];
+      d.vx[i] = vn[0]; d.vy[i] = vn[1]; d.vz[i] = vn[2];
+      d.ax[i] = f[0]; d.ay[i] = f[1]; d.az[i] = f[2];
+      d.jx[i] = f[3]; d.jy[i] = f[4]; d.jz[i] = f[5];
+      d.tick[i] = t_next;
+      d.lev[i] = (unsigned char)nl;
+      if (nl != lv) {
+        atomicAdd(&bk.hist[lv], -1);
+        atomicAdd(&bk.hist[nl], 1);
+      }
+      if (kStep) {
+        // the corrected state predicted to the speculated next block time
+        taylor6((double)(t_spec - t_next) * c.dt_min, xn[0], xn[1], xn[2], vn[0], vn[1], vn[2], f[0], f[1],
+                f[2], f[3], f[4], f[5], o);
+        d.px[i] = o[0]; d.py[i] = o[1]; d.pz[i] = o[2];
+        d.pvx[i] = o[3]; d.pvy[i] = o[4]; d.pvz[i] = o[5];
+        take = nl >= kthr_spec;
+      }
     }
-  const double na1 = norm3(f[0], f[1], f[2]);
-    const double nj1 = norm3(f[3], f[4], f[5]);
-    const double na2 = norm3(a2e[0], a2e[1], a2e[2]);
-    const double na3 = norm3(a3[0], a3[1], a3[2]);
-    const double dtstar = sqrt(c.eta * (na1 * na2 + nj1 * nj1) / (nj1 * na3 + na2 * na2));
-    const int kc = level_for(dtstar, c.dt_max, c.inv_dt_max, c.kmax);
-    int nl;
-    if (kc >= lv) {
-      nl = kc;
-    } else if (lv >= 1 && (t_next & ((1LL << (c.kmax - lv + 1)) - 1)) == 0) {
-      nl = lv - 1;
-    } else {
-      nl = lv;
-    }
-    if (nl > c.kmax) {
-      nl = c.kmax;
-      atomicAdd(&bk.clamp, 1);
-    }
-    d.x[i] = xn[0]; d.y[i] = xn[1]; d.z[i] = xn[2];
-    d.vx[i] = vn[0]; d.vy[i] = vn[1]; d.vz[i] = vn[2];
-    d.ax[i] = f[0]; d.ay[i] = f[1]; d.az[i] = f[2];
-    d.jx[i] = f[3]; d.jy[i] = f[4]; d.jz[i] = f[5];
-    d.tick[i] = t_next;
-    d.lev[i] = (unsigned char)nl;
-    if (nl != lv) {
-      atomicAdd(&bk.hist[lv], -1);
-      atomicAdd(&bk.hist[nl], 1);
+    if (kStep) {
+      const int pos = wg_append(take, &sc->lcnt[par ^ 1]);
+      if (take) list_store(d, c.n, par ^ 1, pos, i, o, f[0], f[1], f[2], f[3], f[4], f[5], nl, t_spec);
     }
   }
   __syncthreads();
   book_flush(bk, sc, c.kmax, tid);
 }
 
+// The particles that the corrector of a replayed step of parity par did not
+// correct (those not tagged in list par with this step's block time): each
+// predicted to the speculated next block time into the j stream, and those
+// active then appended to list par ^ 1. Workgroups take blocks of kBlock
+// particles.
+__device__ __forceinline__ void predict_rest(const Dev& d, const Consts& c, int blk, int nblk, int par) {
+  const Sched* __restrict__ sc = d.sc;
+  const int n = c.n, tid = threadIdx.x;
+  const int nb = (n + kBlock - 1) / kBlock;
+  if (blk >= nb) return;
+  // The first block's state is requested before the schedule record is read.
+  PState ps = load_pstate(d, min(blk * kBlock + tid, n - 1));
+  long long tg = d.tag[(size_t)par * n + min(blk * kBlock + tid, n - 1)];
+  if (sc->done || sc->refill) return;
+  const long long t_next = sc->t_next;
+  const long long t_spec = t_next + (1LL << (c.kmax - sc->fine));
+  const int kthr_spec = max(0, c.kmax - (int)__builtin_ctzll((unsigned long long)t_spec));
+  for (int b = blk; b < nb; b += nblk) {
+    if (b != blk) {
+      ps = load_pstate(d, min(b * kBlock + tid, n - 1));
+      tg = d.tag[(size_t)par * n + min(b * kBlock + tid, n - 1)];
+    }
+    const int j = b * kBlock + tid;
+    bool take = false;
+    double o[6];
+    if (j < n && tg != t_next) {
+      predict_store(d, j, (double)(t_spec - ps.tick) * c.dt_min, ps, o);
+      take = ps.lev >= kthr_spec;
+    }
+    const int pos = wg_append(take, &d.sc->lcnt[par ^ 1]);
+    if (take) list_store(d, n, par ^ 1, pos, j, o, ps.ax, ps.ay, ps.az, ps.jx, ps.jy, ps.jz, ps.lev, t_spec);
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_correct(Dev d, Consts c) {
-  correct_body(d, c, blockIdx.x, gridDim.x);
+  correct_body<false>(d, c, blockIdx.x, gridDim.x);
+}
+
+// The corrector of a graph-replayed block step of parity par: the first
+// ceil(n / kBlock) workgroups predict the particles this step does not
+// correct (predict_rest), the others correct the active particles
+// (correct_body). The prediction workgroups come first: in a small step they
+// are the longer path (every particle's state, the list counter's round
+// trip), and workgroups start in index order (same-box timing of the
+// N = 16384 integration: 548 ms this way, 563 ms the other way round).
+__global__ __launch_bounds__(kBlock) void k_step_correct(Dev d, Consts c, int par) {
+  const int nb = (c.n + kBlock - 1) / kBlock;
+  if ((int)blockIdx.x < nb)
+    predict_rest(d, c, blockIdx.x, nb, par);
+  else
+    correct_body<true>(d, c, blockIdx.x - nb, gridDim.x - nb, par);
+}
+
+// Prediction of every particle to the next block time into the j stream and
+// list 0 for it (t_end as set before), for a step of parity 0.
+__global__ __launch_bounds__(kBlock) void k_prepare(Dev d, Consts c) {
+  Sched* __restrict__ sc = d.sc;
+  const int n = c.n;
+  const NextStep nx = schedule_wave(sc, c);
+  for (int b = blockIdx.x; b < (n + kBlock - 1) / kBlock; b += gridDim.x) {
+    const PState ps = load_pstate(d, min(b * kBlock + (int)threadIdx.x, n - 1));
+    predict_append(d, c, b, ps, nx.t_next, nx.kthr, 0);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc->spec = nx.t_next << 1;
 }
 
 // Initial block steps (Sec. 2.4 step 3; Sec. 3.2: the same eta from the
@@ -904,82 +1166,38 @@ __global__ __launch_bounds__(kBlock) void k_reduce_out(Dev d, Consts c, double* 
 // list order is not deterministic, but no result depends on it), together
 // with their predicted state (for the force kernel) and their a, jerk and
 // level (for the corrector), stored by list position.
+
 __device__ __forceinline__ void predict_body(const Dev& d, const Consts& c, int mode,
                                              double t_explicit, int blk) {
   Sched* __restrict__ sc = d.sc;
   const int n = c.n, kmax = c.kmax;
-  const double dt_min = c.dt_min;
-  const double* __restrict__ x = d.x;
-  const double* __restrict__ y = d.y;
-  const double* __restrict__ z = d.z;
-  const double* __restrict__ vx = d.vx;
-  const double* __restrict__ vy = d.vy;
-  const double* __restrict__ vz = d.vz;
-  const double* __restrict__ ax = d.ax;
-  const double* __restrict__ ay = d.ay;
-  const double* __restrict__ az = d.az;
-  const double* __restrict__ jx = d.jx;
-  const double* __restrict__ jy = d.jy;
-  const double* __restrict__ jz = d.jz;
-  const long long* __restrict__ tick = d.tick;
-  const unsigned char* __restrict__ lev = d.lev;
-  double* __restrict__ px = d.px;
-  double* __restrict__ py = d.py;
-  double* __restrict__ pz = d.pz;
-  double* __restrict__ pvx = d.pvx;
-  double* __restrict__ pvy = d.pvy;
-  double* __restrict__ pvz = d.pvz;
-  int* __restrict__ active = d.active;
-  double* __restrict__ ix = d.ix;
-  double* __restrict__ iy = d.iy;
-  double* __restrict__ iz = d.iz;
-  double* __restrict__ ivx = d.ivx;
-  double* __restrict__ ivy = d.ivy;
-  double* __restrict__ ivz = d.ivz;
-  double* __restrict__ iax = d.iax;
-  double* __restrict__ iay = d.iay;
-  double* __restrict__ iaz = d.iaz;
-  double* __restrict__ ijx = d.ijx;
-  double* __restrict__ ijy = d.ijy;
-  double* __restrict__ ijz = d.ijz;
-  int* __restrict__ ilev = d.ilev;
   __shared__ long long s_tnext;
-  __shared__ int s_kthr, s_done, s_base;
-  __shared__ int s_wcount[kBlock / 64];
+  __shared__ int s_kthr, s_done;
   const int tid = threadIdx.x;
-  const int j = blk * kBlock + tid;
   // The particle's state does not depend on the schedule: its loads are
   // issued first and overlap the read of the histogram and the clock.
-  const int jj = min(j, n - 1);
-  const double x0 = x[jj], y0 = y[jj], z0 = z[jj];
-  const double v_x = vx[jj], v_y = vy[jj], v_z = vz[jj];
-  const double a_x = ax[jj], a_y = ay[jj], a_z = az[jj];
-  const double j_x = jx[jj], j_y = jy[jj], j_z = jz[jj];
-  const long long tj = tick[jj];
-  const int lj = lev[jj];
+  const PState p = load_pstate(d, min(blk * kBlock + tid, n - 1));
   // The step, by wave 0 (next_step_wave, make_plan_wave).
   const int wave = tid >> 6, lane = tid & 63;
   if (wave == 0) {
-    const int h = lane <= kmax ? sc->hist[lane] : 0;
-    const long long t_now = sc->t_now;
     long long t_next;
     int kthr, nact = 0, done = 0;
     if (mode == kPredAuto) {
-      const NextStep nx = next_step_wave(h, lane, kmax, t_now, sc->t_end, count_bits(n));
+      const NextStep nx = schedule_wave(sc, c);
       t_next = nx.t_next;
       kthr = nx.kthr;
       nact = nx.n_act;
       done = nx.done;
     } else if (mode == kPredAll) {
-      t_next = t_now;
+      t_next = sc->t_now;
       kthr = 0;
       nact = n;
     } else {
-      t_next = t_now;
+      t_next = sc->t_now;
       kthr = kmax + 1;  // nobody active
     }
-    Plan p{};
-    if (blk == 0 && nact > 0) p = make_plan_wave(nact, n, ipl_of(c), lane);
+    Plan pl{};
+    if (blk == 0 && nact > 0) pl = make_plan_wave(nact, n, ipl_of(c), lane);
     if (lane == 0) {
       s_tnext = t_next;
       s_kthr = kthr;
@@ -989,47 +1207,20 @@ __device__ __forceinline__ void predict_body(const Dev& d, const Consts& c, int 
         sc->kthr = kthr;
         sc->n_act = nact;
         sc->done = done;
-        if (nact > 0) sc->plan = p;
+        if (nact > 0) sc->plan = pl;
       }
     }
   }
   __syncthreads();
   if (s_done) return;
-
-  bool act = false;
-  double o[6];
-  if (j < n) {
-    const double dt = (mode == kPredExplicit) ? t_explicit - (double)tj * dt_min
-                                              : (double)(s_tnext - tj) * dt_min;
-    taylor6(dt, x0, y0, z0, v_x, v_y, v_z, a_x, a_y, a_z, j_x, j_y, j_z, o);
-    px[j] = o[0]; py[j] = o[1]; pz[j] = o[2];
-    pvx[j] = o[3]; pvy[j] = o[4]; pvz[j] = o[5];
-    act = lj >= s_kthr;
+  if (mode == kPredExplicit) {
+    // prediction to an explicit time: the j stream only, nobody listed
+    const int j = blk * kBlock + tid;
+    double o[6];
+    if (j < n) predict_store(d, j, t_explicit - (double)p.tick * c.dt_min, p, o);
+    return;
   }
-  // Workgroup compaction of the active flags.
-  const unsigned long long ball = __ballot(act);
-  const int before = __popcll(ball & ((1ULL << lane) - 1ULL));
-  if (lane == 0) s_wcount[wave] = __popcll(ball);
-  __syncthreads();
-  if (tid == 0) {
-    int tot = 0;
-    for (int w = 0; w < kBlock / 64; ++w) {
-      const int c = s_wcount[w];
-      s_wcount[w] = tot;
-      tot += c;
-    }
-    s_base = tot ? atomicAdd(&sc->cnt, tot) : 0;
-  }
-  __syncthreads();
-  if (act) {
-    const int k = s_base + s_wcount[wave] + before;
-    active[k] = j;
-    ix[k] = o[0]; iy[k] = o[1]; iz[k] = o[2];
-    ivx[k] = o[3]; ivy[k] = o[4]; ivz[k] = o[5];
-    iax[k] = a_x; iay[k] = a_y; iaz[k] = a_z;
-    ijx[k] = j_x; ijy[k] = j_y; ijz[k] = j_z;
-    ilev[k] = lj;
-  }
+  predict_append(d, c, blk, p, s_tnext, s_kthr, 0);
 }
 
 __global__ __launch_bounds__(kBlock) void k_predict(Dev d, Consts c, int mode, double t_explicit) {
@@ -1219,9 +1410,11 @@ __global__ void k_load(Sched* __restrict__ sc, int n, int bh, const double* __re
                        double* __restrict__ vz, double* __restrict__ ax, double* __restrict__ ay,
                        double* __restrict__ az, double* __restrict__ jx, double* __restrict__ jy,
                        double* __restrict__ jz, long long* __restrict__ tick,
-                       unsigned char* __restrict__ lev) {
+                       unsigned char* __restrict__ lev, long long* __restrict__ tag) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  tag[i] = -1;
+  tag[n + i] = -1;
   const double mi = m_in[i];
   const double x0 = x_in[3 * i], x1 = x_in[3 * i + 1], x2 = x_in[3 * i + 2];
   const double v0 = v_in[3 * i], v1 = v_in[3 * i + 1], v2 = v_in[3 * i + 2];
@@ -1244,22 +1437,27 @@ __global__ void k_reset_sched(Sched* __restrict__ sc, long long t_now) {
     sc->n_act = 0;
     sc->kthr = 0;
     sc->done = 0;
-    sc->cnt = 0;
+    sc->lcnt[0] = 0;
+    sc->lcnt[1] = 0;
+    sc->spec = -2;  // no list prepared (block time -1)
+    sc->refill = 0;
+    sc->fine = 0;
     sc->nonfinite = 0;
     sc->bad_input = 0;
     sc->block_steps = 0;
     sc->particle_steps = 0;
     sc->pairs = 0;
     sc->clamps = 0;
+    sc->refills = 0;
   }
   if (blockIdx.x == 0 && threadIdx.x <= kMaxLevels) sc->hist[threadIdx.x] = 0;
   if (blockIdx.x == 0 && threadIdx.x < kNactBins) sc->nact_hist[threadIdx.x] = 0;
 }
 
 // N_act of the step in flight, for the force-timing pass (0 when the step was
-// skipped because the stop time was reached).
+// skipped because the stop time was reached, or rebuilt its list).
 __global__ void k_log_nact(const Sched* __restrict__ sc, int* __restrict__ out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *out = sc->done ? 0 : sc->n_act;
+  if (threadIdx.x == 0 && blockIdx.x == 0) *out = (sc->done || sc->refill) ? 0 : sc->n_act;
 }
 
 // Prepares a sequence of automatic steps: sets the stop time and clears the
@@ -1267,7 +1465,8 @@ __global__ void k_log_nact(const Sched* __restrict__ sc, int* __restrict__ out) 
 __global__ void k_set_tend(Sched* __restrict__ sc, long long t_end) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     sc->t_end = t_end;
-    sc->cnt = 0;
+    sc->lcnt[0] = 0;
+    sc->lcnt[1] = 0;
     sc->done = 0;
   }
 }
@@ -1338,9 +1537,11 @@ __global__ void k_set_state(Sched* __restrict__ sc, int n, int kmax, double dt_m
                             double* __restrict__ ay, double* __restrict__ az,
                             double* __restrict__ jx, double* __restrict__ jy,
                             double* __restrict__ jz, long long* __restrict__ tick,
-                            unsigned char* __restrict__ lev) {
+                            unsigned char* __restrict__ lev, long long* __restrict__ tag) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  tag[i] = -1;
+  tag[n + i] = -1;
   bool ok = fin3(xi[3 * i], xi[3 * i + 1], xi[3 * i + 2]) &&
             fin3(vi[3 * i], vi[3 * i + 1], vi[3 * i + 2]) &&
             fin3(ai[3 * i], ai[3 * i + 1], ai[3 * i + 2]) &&
@@ -1474,7 +1675,7 @@ __global__ __launch_bounds__(kBlock) void k_pool_correct(const PoolSlot* __restr
   for (int g = blockIdx.x; g < total; g += gridDim.x) {
     const int k = pool_find(s_off, count, g);
     const PoolSlot& ps = slots[s_order[k]];
-    correct_body(ps.d, ps.c, g - s_off[k], s_n[k]);
+    correct_body<false>(ps.d, ps.c, g - s_off[k], s_n[k]);
   }
 }
 
@@ -1625,7 +1826,7 @@ hipError_t launch_load(const Dev& d, const Consts& c, const double* m, const dou
                        const double* v, hipStream_t s) {
   hipLaunchKernelGGL(k_load, dim3(grid_for(c.n)), dim3(kBlock), 0, s, d.sc, c.n, c.bh, m, x, v, d.m,
                      d.jm, d.x, d.y, d.z, d.vx, d.vy, d.vz, d.ax, d.ay, d.az, d.jx, d.jy, d.jz, d.tick,
-                     d.lev);
+                     d.lev, d.tag);
   return hipGetLastError();
 }
 
@@ -1655,6 +1856,37 @@ hipError_t launch_force(const Dev& d, const Consts& c, hipStream_t s, hipEvent_t
   } else {
     hipLaunchKernelGGL(kern, dim3(c.force_grid), dim3(kBlock), 0, s, d, c);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_step_force(const Dev& d, const Consts& c, int par, hipStream_t s, hipEvent_t ev_start,
+                             hipEvent_t ev_stop) {
+  auto kern = ipl_of(c) == kIPerLaneLarge
+                  ? (c.mixed ? (c.bh >= 0 ? k_step_force<false, true, true, kIPerLaneLarge>
+                                          : k_step_force<false, false, true, kIPerLaneLarge>)
+                             : (c.bh >= 0 ? k_step_force<false, true, false, kIPerLaneLarge>
+                                          : k_step_force<false, false, false, kIPerLaneLarge>))
+              : c.mixed ? (c.bh >= 0 ? k_step_force<false, true, true, kIPerLane>
+                                     : (c.eps2 > 0.0 ? k_step_force<false, false, true, kIPerLane>
+                                                     : k_step_force<true, false, true, kIPerLane>))
+                        : (c.bh >= 0 ? k_step_force<false, true, false, kIPerLane>
+                                     : (c.eps2 > 0.0 ? k_step_force<false, false, false, kIPerLane>
+                                                     : k_step_force<true, false, false, kIPerLane>));
+  if (ev_start) {
+    hipExtLaunchKernelGGL(kern, dim3(c.force_grid), dim3(kBlock), 0, s, ev_start, ev_stop, 0, d, c, par);
+  } else {
+    hipLaunchKernelGGL(kern, dim3(c.force_grid), dim3(kBlock), 0, s, d, c, par);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_step_correct(const Dev& d, const Consts& c, int par, hipStream_t s) {
+  hipLaunchKernelGGL(k_step_correct, dim3(c.correct_grid + grid_for(c.n)), dim3(kBlock), 0, s, d, c, par);
+  return hipGetLastError();
+}
+
+hipError_t launch_prepare(const Dev& d, const Consts& c, hipStream_t s) {
+  hipLaunchKernelGGL(k_prepare, dim3(grid_for(c.n)), dim3(kBlock), 0, s, d, c);
   return hipGetLastError();
 }
 
@@ -1729,7 +1961,7 @@ hipError_t launch_set_state(const Dev& d, const Consts& c, const double* x, cons
                             const double* dt_i, long long t_now, hipStream_t s) {
   hipLaunchKernelGGL(k_set_state, dim3(grid_for(c.n)), dim3(kBlock), 0, s, d.sc, c.n, c.kmax,
                      c.dt_min, t_now, x, v, a, jerk, t_i, dt_i, d.x, d.y, d.z, d.vx, d.vy, d.vz,
-                     d.ax, d.ay, d.az, d.jx, d.jy, d.jz, d.tick, d.lev);
+                     d.ax, d.ay, d.az, d.jx, d.jy, d.jz, d.tick, d.lev, d.tag);
   return hipGetLastError();
 }
 

@@ -82,6 +82,8 @@ def library():
     lib.gd_set_state.argtypes = [_VP, _VP, _VP, _VP, _VP, _VP, _VP, C.c_double]
     lib.gd_stats_get.argtypes = [_VP, C.POINTER(gd_stats)]
     lib.gd_nact_histogram.argtypes = [_VP, C.POINTER(i64)]
+    lib.gd_refills.argtypes = [_VP, C.POINTER(i64)]
+    lib.gd_refills.restype = st
     lib.gd_diagnostics.argtypes = [_VP, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_double),
                                    C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(i64), C.c_int32]
     lib.gd_diagnostics.restype = st
@@ -303,6 +305,13 @@ def gd_nact_histogram(ctx) -> list:
     counts = (C.c_int64 * GD_NACT_BINS)()
     _check(library().gd_nact_histogram(ctx, counts), ctx)
     return [int(c) for c in counts]
+
+
+def gd_refills(ctx) -> int:
+    """Replayed steps that rebuilt their active list instead of stepping."""
+    r = C.c_int64()
+    _check(library().gd_refills(ctx, C.byref(r)), ctx)
+    return int(r.value)
 
 
 def gd_destroy(ctx) -> None:
