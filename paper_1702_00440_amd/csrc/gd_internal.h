@@ -107,11 +107,14 @@ __host__ __device__ inline Plan plan_with(int n_act, int n, int lj, int s_req, i
   int tiles = (n + kTileJ - 1) / kTileJ;
   if (tiles < 1) tiles = 1;
   const int s0 = s_req < 1 ? 1 : (s_req > tiles ? tiles : s_req);
-  const int tps = (tiles + s0 - 1) / s0;  // tiles per slice
+  // it and (in make_plan's plans) s0 are powers of two: shifts, not divisions
+  const int lg_it = (8 - lj) + __builtin_ctz((unsigned)ipl);  // kBlock = 2^8
+  const int tps = (s0 & (s0 - 1)) == 0 ? (tiles + s0 - 1) >> __builtin_ctz((unsigned)s0)
+                                       : (tiles + s0 - 1) / s0;  // tiles per slice
   Plan p;
   p.lj = lj;
   p.it = (kBlock >> lj) * ipl;
-  p.nit = (n_act + p.it - 1) / p.it;
+  p.nit = (n_act + p.it - 1) >> lg_it;
   if (p.nit < 1) p.nit = 1;
   p.s = (tiles + tps - 1) / tps;
   p.len = tps * kTileJ;
@@ -128,7 +131,7 @@ __host__ __device__ inline Plan plan_for_lj(int n_act, int n, int lj, int ipl, b
   int tiles = (n + kTileJ - 1) / kTileJ;
   if (tiles < 1) tiles = 1;
   const int it = (kBlock >> lj) * ipl;
-  int nit = (n_act + it - 1) / it;
+  int nit = (n_act + it - 1) >> ((8 - lj) + __builtin_ctz((unsigned)ipl));  // it = 2^(8 - lj) * ipl
   if (nit < 1) nit = 1;
   int s = 1;
   while (2 * s <= tiles && 2 * s * nit <= kSliceItems) s *= 2;

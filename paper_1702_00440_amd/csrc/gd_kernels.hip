@@ -267,19 +267,15 @@ struct NextStep {
   int fine;  // finest occupied level
 };
 
-// Sum over a wave of values in [0, 2^nbits), by bit slices: a ballot and a
-// population count per bit, no lane-to-lane data movement.
-__device__ __forceinline__ int wave_sum_bits(int v, int nbits) {
-  int s = 0;
-  for (int b = 0; b < nbits; ++b) s += __popcll(__ballot((v >> b) & 1)) << b;
-  return s;
-}
-
-// Bits needed for counts up to n.
-__host__ __device__ inline int count_bits(int n) {
-  int b = 1;
-  while ((1LL << b) <= n) ++b;
-  return b;
+// Sum over a wave (every lane gets it), by a register butterfly.
+__device__ __forceinline__ int wave_sum(int v) {
+  v += xor_partner_i<32>(v);
+  v += xor_partner_i<16>(v);
+  v += xor_partner_i<8>(v);
+  v += xor_partner_i<4>(v);
+  v += xor_partner_i<2>(v);
+  v += xor_partner_i<1>(v);
+  return v;
 }
 
 // The next block step from the level histogram (Sec. 2.4 steps 5-6),
@@ -288,10 +284,10 @@ __host__ __device__ inline int count_bits(int n) {
 // so the next block time is the next multiple of the smallest step present
 // (the finest occupied level is the highest set bit of a ballot), the active
 // particles are those with level >= kmax - ctz(t_next), and their number is
-// the histogram's tail sum (a bit-sliced wave sum). Every lane returns the
+// the histogram's tail sum (a wave sum). Every lane returns the
 // same result.
 __device__ __forceinline__ NextStep next_step_wave(int h, int lane, int kmax, long long t_now,
-                                                   long long t_end, int nbits) {
+                                                   long long t_end) {
   const unsigned long long occ = __ballot(h > 0);
   const int kmx = occ ? 63 - __clzll((long long)occ) : 0;
   const int sh = kmax - kmx;
@@ -299,7 +295,7 @@ __device__ __forceinline__ NextStep next_step_wave(int h, int lane, int kmax, lo
   r.t_next = ((t_now >> sh) + 1) << sh;
   const int tz = __builtin_ctzll((unsigned long long)r.t_next);
   r.kthr = max(0, kmax - tz);
-  r.n_act = wave_sum_bits(lane >= r.kthr ? h : 0, nbits);
+  r.n_act = wave_sum(lane >= r.kthr ? h : 0);
   r.done = r.t_next > t_end;
   r.fine = kmx;
   return r;
@@ -421,7 +417,7 @@ __device__ __forceinline__ void predict_append(const Dev& d, const Consts& c, in
 __device__ __forceinline__ NextStep schedule_wave(const Sched* __restrict__ sc, const Consts& c) {
   const int lane = threadIdx.x & 63;
   const int h = lane <= c.kmax ? sc->hist[lane] : 0;
-  return next_step_wave(h, lane, c.kmax, sc->t_now, sc->t_end, count_bits(c.n));
+  return next_step_wave(h, lane, c.kmax, sc->t_now, sc->t_end);
 }
 
 // ---------------------------------------------------------------------------
@@ -682,7 +678,9 @@ __device__ __forceinline__ void force_body(const Dev& d, const Consts& c, int bl
     // The step from the level histogram, in every wave (each wave gets the
     // same result), then the check of the prepared list and j stream.
     const NextStep nx = schedule_wave(sc, c);
-    const long long prepared = __hip_atomic_load(&sc->spec, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // A plain 64-bit load (one access: either the old word or the new one);
+    // an agent-scope atomic load would bypass the caches.
+    const long long prepared = __hip_atomic_load(&sc->spec, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     if (nx.done) {
       if (blk == 0 && tid == 0) {
         sc->done = 1;
@@ -887,7 +885,7 @@ __device__ __forceinline__ void correct_body(const Dev& d, const Consts& c, int 
       // the list this step's corrector would have built next stays free
       if (blk == 0 && tid == 0) {
         sc->lcnt[par] = 0;
-        if (sc->refill) sc->refills += 1;
+        if (sc->refill) atomicAdd((unsigned long long*)&sc->refills, 1ULL);
       }
       return;
     }
@@ -909,10 +907,12 @@ __device__ __forceinline__ void correct_body(const Dev& d, const Consts& c, int 
   book_init(bk, tid);
   __syncthreads();
   if (blk == 0 && tid == 0) {
-    sc->block_steps += 1;
-    sc->particle_steps += n_act;
-    sc->pairs += (long long)n_act * c.n;
-    if (n_act > 0) sc->nact_hist[31 - __clz(n_act)] += 1;
+    // Counters by atomics whose result is not used: no memory round trip
+    // before the wave goes on.
+    atomicAdd((unsigned long long*)&sc->block_steps, 1ULL);
+    atomicAdd((unsigned long long*)&sc->particle_steps, (unsigned long long)n_act);
+    atomicAdd((unsigned long long*)&sc->pairs, (unsigned long long)n_act * (unsigned long long)c.n);
+    if (n_act > 0) atomicAdd((unsigned long long*)&sc->nact_hist[31 - __clz(n_act)], 1ULL);
     sc->t_now = t_next;
     if (kStep) {
       sc->lcnt[par] = 0;
