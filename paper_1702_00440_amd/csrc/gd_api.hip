@@ -181,7 +181,7 @@ Consts consts_of(const gd_params* p, int64_t n, int kmax, int ipl) {
   c.eps2_bh = p->bh_index >= 0 ? p->eps_bh * p->eps_bh : c.eps2;
   c.mixed = (p->flags & GD_FLAG_MIXED) ? 1 : 0;
   const Plan p1 = make_plan(1, (int)n, ipl);
-  c.lj1_ipl = p1.lj | (ipl << 8);
+  c.lj1_ipl = p1.lj | (ipl << 8);  // n1 = 0: see make_consts
   c.s1 = p1.s;
   c.part_cs = partial_rows(n, ipl);
   return c;
@@ -194,6 +194,15 @@ Consts make_consts(const gd_params* p, int64_t n, int kmax, bool pool) {
   const int ipl = pool ? kIPerLane : ipl_for(p, n);
   Consts c = consts_of(p, n, kmax, ipl);
   launch_grids((int)n, ipl, &c.force_grid, &c.correct_grid);
+  // n1: every block of up to n1 particles has the one-particle decomposition
+  // (the kernels then take one_plan instead of make_plan's search)
+  int n1 = 1;
+  while (n1 < n && n1 < 65535) {
+    const Plan q = make_plan(n1 + 1, (int)n, ipl);
+    if (q.lj != lj1_of(c) || q.s != c.s1) break;
+    ++n1;
+  }
+  c.lj1_ipl |= n1 << 16;
   return c;
 }
 

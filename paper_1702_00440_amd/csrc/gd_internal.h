@@ -217,15 +217,35 @@ struct Consts {
   int mixed;         // 1: pair arithmetic in mixed precision (GD_FLAG_MIXED)
   double dt_min, dt_max, eta, eps2, eps2_bh;
   double inv_dt_min, inv_dt_max;  // exact reciprocals (powers of two)
-  // The decomposition of a one-particle block (log2 lanes per i; j slices s1)
-  // and the force kernel's i count per lane, packed as lj1 | ipl << 8: one
-  // field more would split the corrector's kernel-argument loads into two
-  // dependent batches (its scalar registers are full).
+  // The decomposition of a one-particle block (log2 lanes per i; j slices
+  // s1), the force kernel's i count per lane, and the largest block size up
+  // to which every block has the one-particle decomposition (at most
+  // 65535), packed as lj1 | ipl << 8 | n1 << 16: one field more would split
+  // the corrector's kernel-argument loads into two dependent batches (its
+  // scalar registers are full).
   int lj1_ipl, s1;
   long long part_cs;  // component stride of the partial-force buffer (partial_rows(n, ipl))
 };
 __host__ __device__ inline int lj1_of(const Consts& c) { return c.lj1_ipl & 255; }
-__host__ __device__ inline int ipl_of(const Consts& c) { return c.lj1_ipl >> 8; }
+__host__ __device__ inline int ipl_of(const Consts& c) { return (c.lj1_ipl >> 8) & 255; }
+__host__ __device__ inline int n1_of(const Consts& c) { return (int)((unsigned)c.lj1_ipl >> 16); }
+
+// make_plan(n_act, n, ipl_of(c)) for n_act <= n1_of(c): the one-particle
+// decomposition with the i tiles that n_act needs (a few shifts, where
+// make_plan's search is a long dependent chain).
+__host__ __device__ inline Plan one_plan(int n_act, int n, const Consts& c) {
+  const int lj = lj1_of(c), ipl = ipl_of(c);
+  const int tiles = (n + kTileJ - 1) / kTileJ;
+  Plan p;
+  p.lj = lj;
+  p.it = (kBlock >> lj) * ipl;
+  p.nit = (n_act + p.it - 1) >> ((8 - lj) + __builtin_ctz((unsigned)ipl));
+  if (p.nit < 1) p.nit = 1;
+  p.s = c.s1;
+  p.len = ((tiles + c.s1 - 1) / c.s1) * kTileJ;
+  p.items = p.nit * p.s;
+  return p;
+}
 
 // Lanes the corrector gives one active particle: one per j slice of the
 // force plan (rounded up to a power of two), at most a wave.

@@ -707,7 +707,7 @@ __device__ __forceinline__ void force_body(const Dev& d, const Consts& c, int bl
       return;
     }
     n_act = nx.n_act;
-    p = make_plan_wave(n_act, n, ipl_of(c), tid & 63);
+    p = n_act <= n1_of(c) ? one_plan(n_act, n, c) : make_plan_wave(n_act, n, ipl_of(c), tid & 63);
     if (blk == 0 && tid == 0) {
       sc->t_next = nx.t_next;
       sc->kthr = nx.kthr;
@@ -1197,7 +1197,7 @@ __device__ __forceinline__ void predict_body(const Dev& d, const Consts& c, int 
       kthr = kmax + 1;  // nobody active
     }
     Plan pl{};
-    if (blk == 0 && nact > 0) pl = make_plan_wave(nact, n, ipl_of(c), lane);
+    if (blk == 0 && nact > 0) pl = nact <= n1_of(c) ? one_plan(nact, n, c) : make_plan_wave(nact, n, ipl_of(c), lane);
     if (lane == 0) {
       s_tnext = t_next;
       s_kthr = kthr;
