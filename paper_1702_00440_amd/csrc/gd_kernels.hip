@@ -295,7 +295,9 @@ __device__ __forceinline__ NextStep next_step_wave(int h, int lane, int kmax, lo
   r.t_next = ((t_now >> sh) + 1) << sh;
   const int tz = __builtin_ctzll((unsigned long long)r.t_next);
   r.kthr = max(0, kmax - tz);
-  r.n_act = wave_sum(lane >= r.kthr ? h : 0);
+  // (read back from lane 0: the compiler then knows the count is uniform and
+  // keeps the decomposition and the loops that depend on it scalar)
+  r.n_act = __builtin_amdgcn_readfirstlane(wave_sum(lane >= r.kthr ? h : 0));
   r.done = r.t_next > t_end;
   r.fine = kmx;
   return r;
@@ -318,6 +320,19 @@ __device__ __forceinline__ Plan make_plan_wave(int n_act, int n, int ipl, int la
   q.s = __builtin_amdgcn_readlane(p.s, first);
   q.len = __builtin_amdgcn_readlane(p.len, first);
   q.items = __builtin_amdgcn_readlane(p.items, first);
+  return q;
+}
+
+// A plan that every lane of the wave holds, read back from lane 0 so that its
+// fields live in scalar registers.
+__device__ __forceinline__ Plan uniform_plan(const Plan& p) {
+  Plan q;
+  q.lj = __builtin_amdgcn_readfirstlane(p.lj);
+  q.it = __builtin_amdgcn_readfirstlane(p.it);
+  q.nit = __builtin_amdgcn_readfirstlane(p.nit);
+  q.s = __builtin_amdgcn_readfirstlane(p.s);
+  q.len = __builtin_amdgcn_readfirstlane(p.len);
+  q.items = __builtin_amdgcn_readfirstlane(p.items);
   return q;
 }
 
@@ -680,7 +695,12 @@ __device__ __forceinline__ void force_body(const Dev& d, const Consts& c, int bl
     const NextStep nx = schedule_wave(sc, c);
     // A plain 64-bit load (one access: either the old word or the new one);
     // an agent-scope atomic load would bypass the caches.
-    const long long prepared = __hip_atomic_load(&sc->spec, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    const long long word = __hip_atomic_load(&sc->spec, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    // (the word is the same in every lane; from lane 0 the branches on it are
+    // uniform)
+    const long long prepared =
+        (long long)(((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(word >> 32)) << 32) |
+                    (unsigned)__builtin_amdgcn_readfirstlane((int)word));
     if (nx.done) {
       if (blk == 0 && tid == 0) {
         sc->done = 1;
@@ -708,6 +728,7 @@ __device__ __forceinline__ void force_body(const Dev& d, const Consts& c, int bl
     }
     n_act = nx.n_act;
     p = n_act <= n1_of(c) ? one_plan(n_act, n, c) : make_plan_wave(n_act, n, ipl_of(c), tid & 63);
+    p = uniform_plan(p);
     if (blk == 0 && tid == 0) {
       sc->t_next = nx.t_next;
       sc->kthr = nx.kthr;
@@ -718,10 +739,10 @@ __device__ __forceinline__ void force_body(const Dev& d, const Consts& c, int bl
       sc->refill = 0;
     }
   } else {
-    if (sc->done) return;
-    n_act = sc->n_act;
+    if (__builtin_amdgcn_readfirstlane(sc->done)) return;
+    n_act = __builtin_amdgcn_readfirstlane(sc->n_act);
     if (n_act <= 0) return;
-    p = sc->plan;
+    p = uniform_plan(sc->plan);
   }
   if (blk >= p.items) return;
   // Same lanes per i and slices: same tile size, slice length and item map.
@@ -1586,6 +1607,24 @@ __device__ __forceinline__ int pool_find(const int* off, int count, int g) {
   return k;
 }
 
+// Work item g of a pool launch: the cluster's slot, the workgroup index
+// within that cluster's launch and (n given) its number of workgroups. The
+// same in every lane; read back from lane 0 so that the slot's record is
+// read with scalar loads and the cluster's loops stay scalar.
+struct PoolItem {
+  int slot, blk, nblk;
+};
+
+__device__ __forceinline__ PoolItem pool_item(const int* off, const int* order, const int* n, int count,
+                                              int g) {
+  const int k = __builtin_amdgcn_readfirstlane(pool_find(off, count, g));
+  PoolItem it;
+  it.slot = __builtin_amdgcn_readfirstlane(order[k]);
+  it.blk = g - __builtin_amdgcn_readfirstlane(off[k]);
+  it.nblk = n ? __builtin_amdgcn_readfirstlane(n[k]) : 0;
+  return it;
+}
+
 __global__ __launch_bounds__(kBlock) void k_pool_predict(const PoolSlot* __restrict__ slots,
                                                          const PoolTable* __restrict__ tab) {
   __shared__ int s_off[kMaxPool + 1], s_order[kMaxPool];
@@ -1596,9 +1635,9 @@ __global__ __launch_bounds__(kBlock) void k_pool_predict(const PoolSlot* __restr
   __syncthreads();
   const int total = s_off[count];
   for (int g = blockIdx.x; g < total; g += gridDim.x) {
-    const int k = pool_find(s_off, count, g);
-    const PoolSlot& ps = slots[s_order[k]];
-    predict_body(ps.d, ps.c, kPredAuto, 0.0, g - s_off[k]);
+    const PoolItem it = pool_item(s_off, s_order, nullptr, count, g);
+    const PoolSlot& ps = slots[it.slot];
+    predict_body(ps.d, ps.c, kPredAuto, 0.0, it.blk);
   }
 }
 
@@ -1626,22 +1665,21 @@ __device__ __forceinline__ void pool_force_body(const PoolSlot* __restrict__ slo
   __syncthreads();
   const int total = s_off[count];
   for (int g = blockIdx.x; g < total; g += gridDim.x) {
-    const int k = pool_find(s_off, count, g);
-    const PoolSlot& ps = slots[s_order[k]];
-    force_body<false, false, kMixed, kIPerLane>(ps.d, ps.c, g - s_off[k], s_n[k]);
+    const PoolItem it = pool_item(s_off, s_order, s_n, count, g);
+    const PoolSlot& ps = slots[it.slot];
+    force_body<false, false, kMixed, kIPerLane>(ps.d, ps.c, it.blk, it.nblk);
   }
 }
 
-// The FP64 variant fits 128 VGPRs (4 waves per SIMD) with its few spills
-// outside the loops; the mixed one would spill inside the tile loop there and
-// runs at 3 waves per SIMD instead.
+// Both variants fit 128 VGPRs (4 waves per SIMD) without spills, once the
+// cluster's record is read with scalar loads (pool_item).
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_pool_force(
     const PoolSlot* __restrict__ slots, const PoolTable* __restrict__ tab) {
   pool_force_body<false>(slots, tab);
 }
 
-__global__ __launch_bounds__(kBlock) void k_pool_force_mixed(const PoolSlot* __restrict__ slots,
-                                                             const PoolTable* __restrict__ tab) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_pool_force_mixed(
+    const PoolSlot* __restrict__ slots, const PoolTable* __restrict__ tab) {
   pool_force_body<true>(slots, tab);
 }
 
@@ -1673,9 +1711,9 @@ __global__ __launch_bounds__(kBlock) void k_pool_correct(const PoolSlot* __restr
   __syncthreads();
   const int total = s_off[count];
   for (int g = blockIdx.x; g < total; g += gridDim.x) {
-    const int k = pool_find(s_off, count, g);
-    const PoolSlot& ps = slots[s_order[k]];
-    correct_body<false>(ps.d, ps.c, g - s_off[k], s_n[k]);
+    const PoolItem it = pool_item(s_off, s_order, s_n, count, g);
+    const PoolSlot& ps = slots[it.slot];
+    correct_body<false>(ps.d, ps.c, it.blk, it.nblk);
   }
 }
 
