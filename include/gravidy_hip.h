@@ -228,6 +228,16 @@ gd_status gd_correct(gd_ctx* c);
 gd_status gd_step_to(gd_ctx* c, double t_end, gd_stats* st);
 
 /*
+ * Progress report for long integrations: with interval_s > 0, gd_step_to
+ * writes a line to stderr (current time, t_end, block and particle steps so
+ * far, seconds since the call began) whenever it reads the device schedule
+ * after a batch of block steps and interval_s seconds have passed since its
+ * last line. 0 (the default) turns it off. Host-only; results are unchanged.
+ * Errors: GD_EINVAL for a NULL context or a negative or non-finite interval.
+ */
+gd_status gd_progress(gd_ctx* c, double interval_s);
+
+/*
  * Energy of the synchronised state, Eq. (2) with G = 1: ekin = 1/2 sum m v^2;
  * epot = -sum_{i<j} m_i m_j / sqrt(|r_ij|^2 + eps^2) (softened; the quantity
  * the softened dynamics conserve); epot_unsoft (may be NULL) the same with

@@ -16,6 +16,7 @@
 #include <limits>
 #include <mutex>
 #include <algorithm>
+#include <chrono>
 #include <string>
 #include <vector>
 
@@ -236,6 +237,11 @@ struct gd_ctx {
   bool synced = true;       // every particle at t_now
   long long t_now = 0;      // host copy, valid when synced
   double e0 = 0, e_last = 0;
+  // Progress report of gd_step_to (0: off): at most one line per interval,
+  // written when the host reads the schedule record of a finished replay.
+  double progress_s = 0.0;
+  double prog_target = 0.0;
+  std::chrono::steady_clock::time_point prog_t0, prog_last;
   std::string err;
 
   gd_status fail(gd_status st, const char* fmt, ...) {
@@ -260,6 +266,19 @@ struct gd_ctx {
   } while (0)
 
 namespace {
+
+// One progress line from the schedule record the host holds (h_sc), if the
+// interval has passed since the last one.
+void report_progress(gd_ctx* c) {
+  if (c->progress_s <= 0.0) return;
+  const auto now = std::chrono::steady_clock::now();
+  if (std::chrono::duration<double>(now - c->prog_last).count() < c->progress_s) return;
+  c->prog_last = now;
+  std::fprintf(stderr, "gd_step_to: t = %.9g of %.9g, %lld block steps, %lld particle steps, %.1f s\n",
+               (double)c->h_sc->t_now * c->p.dt_min, c->prog_target, c->h_sc->block_steps,
+               c->h_sc->particle_steps, std::chrono::duration<double>(now - c->prog_t0).count());
+  std::fflush(stderr);
+}
 
 gd_status read_sched(gd_ctx* c) {
   GD_TRY(c->hip(hipMemcpyAsync(c->h_sc, c->d.sc, sizeof(Sched), hipMemcpyDeviceToHost, c->stream),
@@ -630,6 +649,7 @@ gd_status replay_chunk(gd_ctx* c, long long chunk_end) {
       (void)hipStreamSynchronize(c->stream);
       return c->fail(GD_ENONFINITE, "non-finite acceleration or jerk");
     }
+    report_progress(c);
     adv = c->h_sc->t_now - t_prev;
     t_prev = c->h_sc->t_now;
     if (c->h_sc->t_now >= chunk_end) return GD_OK;
@@ -661,6 +681,8 @@ gd_status gd_step_to(gd_ctx* c, double t_end, gd_stats* st) {
     GD_TRY(build_graph(c, 1));
   }
   c->phase = kIdle;
+  c->prog_t0 = c->prog_last = std::chrono::steady_clock::now();
+  c->prog_target = t_end;
   GD_TRY(read_sched(c));
   long long steps_before = c->h_sc->block_steps, pairs_before = c->h_sc->pairs;
   bool prepared = false;
@@ -693,6 +715,7 @@ gd_status gd_step_to(gd_ctx* c, double t_end, gd_stats* st) {
                     "read log"));
       GD_TRY(read_sched(c));
       if (c->h_sc->nonfinite) return c->fail(GD_ENONFINITE, "non-finite acceleration or jerk");
+      report_progress(c);
       // The steps that computed a force logged their N_act (the others, past
       // the stop time or rebuilding their list, logged 0).
       const long long ran = c->h_sc->block_steps - steps_before;
@@ -722,6 +745,14 @@ gd_status gd_step_to(gd_ctx* c, double t_end, gd_stats* st) {
   }
   c->synced = true;
   if (st) GD_TRY(gd_stats_get(c, st));
+  return GD_OK;
+}
+
+gd_status gd_progress(gd_ctx* c, double interval_s) {
+  if (!c) return GD_EINVAL;
+  if (!(interval_s >= 0.0) || !std::isfinite(interval_s))
+    return c->fail(GD_EINVAL, "the progress interval must be finite and >= 0");
+  c->progress_s = interval_s;
   return GD_OK;
 }
 

@@ -77,6 +77,7 @@ def library():
     lib.gd_active.argtypes = [_VP, _VP, C.POINTER(i64)]
     lib.gd_correct.argtypes = [_VP]
     lib.gd_step_to.argtypes = [_VP, C.c_double, C.POINTER(gd_stats)]
+    lib.gd_progress.argtypes = [_VP, C.c_double]
     lib.gd_energy.argtypes = [_VP, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]
     lib.gd_get_state.argtypes = [_VP, _VP, _VP, _VP, _VP, _VP, _VP, C.POINTER(C.c_double)]
     lib.gd_set_state.argtypes = [_VP, _VP, _VP, _VP, _VP, _VP, _VP, C.c_double]
@@ -253,6 +254,10 @@ def gd_step_to(ctx, t_end: float) -> dict:
     st = gd_stats()
     _check(library().gd_step_to(ctx, float(t_end), C.byref(st)), ctx)
     return st.as_dict()
+
+
+def gd_progress(ctx, interval_s: float) -> None:
+    _check(library().gd_progress(ctx, float(interval_s)), ctx)
 
 
 def gd_energy(ctx, unsoftened: bool = False):

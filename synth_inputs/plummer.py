@@ -151,7 +151,6 @@ WORKLOADS = {
     "plummer_imf_n262144": dict(n=262144, seed=5, eps=1e-4, eta=0.01, dt_max=0.125, dt_min=2.0 ** -22,
                                 t_end=0.125, imf=True),
     # 2^20 equal-mass stars plus a central particle of mass 0.01 at rest at the origin
-    # (dt_max 1/64: the integration to 1/8 runs as 8 synchronised chunks)
-    "plummer_bh_n1048576": dict(n=1048576 + 1, n_stars=1048576, seed=7, eps=1e-4, eps_bh=1e-6, m_bh=0.01,
-                                eta=0.01, dt_max=1.0 / 64, dt_min=2.0 ** -22, t_end=0.125),
+    "plummer_bh_n1048576": dict(n=1048576 + 1, n_stars=1048576, seed=5, eps=1e-4, eps_bh=1e-6, m_bh=0.01,
+                                eta=0.01, dt_max=0.125, dt_min=2.0 ** -22, t_end=0.125),
 }

@@ -87,7 +87,7 @@ def test_run_against_oracle(system):
 @pytest.mark.parametrize("flags,tol", [(g.GD_FLAG_MIXED, 2e-6), (0, 1e-12)])
 def test_full_size_sampled(flags, tol):
     """The full central-particle workload: 2^20 stars plus the central particle
-    (seed 7, dt_min 2^-22), in mixed precision (its configuration) and FP64.
+    (seed 5, dt_min 2^-22), in mixed precision (its configuration) and FP64.
     Initial forces of 1024 random stars, the central particle and its 64
     nearest stars against the oracle's compensated sums (mixed: 2e-6, FP64:
     1e-12 per particle); then 3 block steps from the GPU's state with the
@@ -96,7 +96,7 @@ def test_full_size_sampled(flags, tol):
     within the mixed error of a power of two may take the neighbouring level:
     at most one such tie per step, a factor of exactly 2)."""
     ns = 1 << 20
-    m, x, v = plummer_with_bh(ns, 7)
+    m, x, v = plummer_with_bh(ns, 5)
     cl = g.Cluster(m, x, v, eta=ETA, eps=EPS, dt_max=DTMAX, dt_min=DTMIN, device=DEV, eps_bh=EPS_BH,
                    bh_index=ns, flags=flags)
     r = np.linalg.norm(x[:ns], axis=1)

@@ -312,6 +312,32 @@ def test_deterministic_and_resumable():
         cl.close()
 
 
+def test_progress_lines_follow_the_integration(capfd):
+    """gd_progress with a tiny interval reports after every batch of replayed
+    steps: times never decrease, the last line is at t_end, the step counts
+    match the statistics, and the results equal those of a silent run."""
+    n = 1024
+    m, x, v = plummer(n, 4)
+    quiet = g.Cluster(m, x, v, eta=ETA, eps=EPS, device=DEV)
+    sq = g.gd_step_to(quiet.ctx, 0.25)
+    loud = g.Cluster(m, x, v, eta=ETA, eps=EPS, device=DEV)
+    g.gd_progress(loud.ctx, 1e-9)
+    capfd.readouterr()
+    sl = g.gd_step_to(loud.ctx, 0.25)
+    err = capfd.readouterr().err
+    lines = [ln for ln in err.splitlines() if ln.startswith("gd_step_to: t = ")]
+    assert len(lines) >= 2
+    ts = [float(ln.split()[3]) for ln in lines]
+    assert all(b >= a for a, b in zip(ts, ts[1:])) and ts[-1] == 0.25
+    assert f"{sl['block_steps']} block steps" in lines[-1]
+    assert sl == sq
+    np.testing.assert_array_equal(host(loud.state()[0]), host(quiet.state()[0]))
+    with pytest.raises(g.GdError):
+        g.gd_progress(loud.ctx, -1.0)
+    for cl in (quiet, loud):
+        cl.close()
+
+
 def test_error_paths():
     n = 64
     m, x, v = plummer(n, 4)

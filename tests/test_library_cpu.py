@@ -141,6 +141,7 @@ def test_null_context_is_rejected():
     assert lib.gd_predict(None, None) == g.GD_EINVAL
     assert lib.gd_correct(None) == g.GD_EINVAL
     assert lib.gd_step_to(None, 1.0, None) == g.GD_EINVAL
+    assert lib.gd_progress(None, 1.0) == g.GD_EINVAL
     counts = (C.c_int64 * g.GD_NACT_BINS)()
     assert lib.gd_nact_histogram(None, counts) == g.GD_EINVAL
     assert lib.gd_profile_buckets(None, None, None, None, None) == g.GD_EINVAL
