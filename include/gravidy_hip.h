@@ -88,6 +88,9 @@ typedef struct {
   int64_t dtmin_clamps;       /* times a step was clamped at dt_min */
   double e0;                  /* energy at gd_init (kinetic + softened potential) */
   double e;                   /* energy at the last synchronised time gd_step_to reached */
+  double wall_s;              /* host wall-clock seconds spent in gd_step_to since gd_init /
+                                 gd_reinit / gd_set_state (pools: from gd_pool_admit to the
+                                 replay that finished the cluster) */
 } gd_stats;
 
 /*

@@ -237,6 +237,7 @@ struct gd_ctx {
   bool synced = true;       // every particle at t_now
   long long t_now = 0;      // host copy, valid when synced
   double e0 = 0, e_last = 0;
+  double wall_s = 0.0;  // host seconds spent in gd_step_to since the state was set
   // Progress report of gd_step_to (0: off): at most one line per interval,
   // written when the host reads the schedule record of a finished replay.
   double progress_s = 0.0;
@@ -375,6 +376,7 @@ gd_status initialise(gd_ctx* c, const double* m, const double* x, const double* 
   GD_TRY(energy_now(c, 0, e));
   c->e0 = c->e_last = e[0] + e[1];
   c->t_now = 0;
+  c->wall_s = 0.0;
   c->synced = true;
   c->phase = kIdle;
   return GD_OK;
@@ -744,6 +746,7 @@ gd_status gd_step_to(gd_ctx* c, double t_end, gd_stats* st) {
     c->e_last = e[0] + e[1];
   }
   c->synced = true;
+  c->wall_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - c->prog_t0).count();
   if (st) GD_TRY(gd_stats_get(c, st));
   return GD_OK;
 }
@@ -821,6 +824,7 @@ gd_status gd_set_state(gd_ctx* c, const double* x, const double* v, const double
   GD_TRY(read_sched(c));
   if (c->h_sc->bad_input) return c->fail(GD_EINVAL, "invalid state (times, steps or non-finite values)");
   c->t_now = tn;
+  c->wall_s = 0.0;
   c->phase = kIdle;
   // Synchronised only when every particle sits at t_now.
   c->synced = (tn % (1LL << c->c.kmax)) == 0;
@@ -855,6 +859,7 @@ gd_status gd_stats_get(gd_ctx* c, gd_stats* st) {
   st->dtmin_clamps = c->h_sc->clamps;
   st->e0 = c->e0;
   st->e = c->e_last;
+  st->wall_s = c->wall_s;
   return GD_OK;
 }
 
@@ -1106,6 +1111,8 @@ struct PoolSlotHost {
   long long t_end = 0;
   double e0 = 0.0;
   gd_status status = GD_OK;
+  // host clock at admission and at retirement (the replay that finished it)
+  std::chrono::steady_clock::time_point t_admit, t_done;
   Dev d{};
   Consts c{};
 };
@@ -1303,6 +1310,7 @@ gd_status gd_pool_admit(gd_pool* P, int64_t n, const double* m, const double* x,
   if (!pool_place(P, L.total, &off)) return P->fail(GD_ENOMEM, "no room in the arena");
   PoolSlotHost& s = P->slots[sl];
   s = PoolSlotHost();
+  s.t_admit = std::chrono::steady_clock::now();
   s.used = true;
   s.n = n;
   s.off = off;
@@ -1364,6 +1372,7 @@ gd_status gd_pool_run(gd_pool* P, int32_t* finished, int32_t* n_finished) {
     const bool failed = st.nonfinite != 0;
     if (st.t_now >= s.t_end || failed) {
       s.resident = false;
+      s.t_done = std::chrono::steady_clock::now();
       s.status = failed ? GD_ENONFINITE : GD_OK;
       changed = true;
       if (finished) finished[*n_finished] = sl;
@@ -1393,6 +1402,7 @@ gd_status gd_pool_result(gd_pool* P, int32_t sl, double* x, double* v, gd_stats*
     st->dtmin_clamps = ps.clamps;
     st->e0 = s.e0;
     st->e = e;
+    st->wall_s = std::chrono::duration<double>(s.t_done - s.t_admit).count();
   } else {
     GD_TRY(P->hip(hipStreamSynchronize(P->stream), "synchronise"));
   }

@@ -43,7 +43,7 @@ class gd_params(C.Structure):
 class gd_stats(C.Structure):
     _fields_ = [("t", C.c_double), ("block_steps", C.c_int64), ("particle_steps", C.c_int64),
                 ("pair_interactions", C.c_int64), ("dtmin_clamps", C.c_int64),
-                ("e0", C.c_double), ("e", C.c_double)]
+                ("e0", C.c_double), ("e", C.c_double), ("wall_s", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

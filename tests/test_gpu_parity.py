@@ -330,7 +330,8 @@ def test_progress_lines_follow_the_integration(capfd):
     ts = [float(ln.split()[3]) for ln in lines]
     assert all(b >= a for a, b in zip(ts, ts[1:])) and ts[-1] == 0.25
     assert f"{sl['block_steps']} block steps" in lines[-1]
-    assert sl == sq
+    assert {k: v for k, v in sl.items() if k != "wall_s"} == {k: v for k, v in sq.items() if k != "wall_s"}
+    assert sl["wall_s"] > 0.0
     np.testing.assert_array_equal(host(loud.state()[0]), host(quiet.state()[0]))
     with pytest.raises(g.GdError):
         g.gd_progress(loud.ctx, -1.0)

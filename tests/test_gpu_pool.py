@@ -67,6 +67,7 @@ def test_pool_results_equal_alone_bitwise():
         assert st["block_steps"] == sa["block_steps"] and st["particle_steps"] == sa["particle_steps"]
         assert st["t"] == t_end
         assert st["e"] == sa["e"] and st["e0"] == sa["e0"]
+        assert st["wall_s"] > 0.0 and sa["wall_s"] > 0.0
         g.gd_pool_release(pool, sl)
     g.gd_pool_destroy(pool)
 
