@@ -1600,11 +1600,31 @@ __global__ void k_set_state(Sched* __restrict__ sc, int n, int kmax, double dt_m
 
 constexpr int kPoolGrid = 1024;
 
-// Finds the entry k with off[k] <= g < off[k + 1] (count entries, off in LDS).
+static_assert(kMaxPool <= 64, "one wave holds the table of a pool launch");
+
+// The last entry k with off[k] <= g (count entries, off in LDS, off[0] = 0,
+// non-decreasing: clusters without work have equal offsets), by the whole
+// wave in one step: lane l tests entry l + 1, and k is the number that pass.
+// Every lane of the wave must be active.
 __device__ __forceinline__ int pool_find(const int* off, int count, int g) {
-  int k = 0;
-  while (k + 1 < count && off[k + 1] <= g) ++k;
-  return k;
+  const int e = (threadIdx.x & 63) + 1;
+  return __popcll(__ballot(e < count && off[e] <= g));
+}
+
+// off[k] = n[0] + ... + n[k - 1] for k = 0..count (count <= 64, arrays in
+// LDS), by the first wave: an inclusive scan of n across its lanes. The
+// caller synchronises the workgroup before and after.
+__device__ __forceinline__ void pool_offsets(const int* n, int count, int* off) {
+  const int tid = threadIdx.x;
+  if (tid >= 64) return;
+  int v = tid < count ? n[tid] : 0;
+#pragma unroll
+  for (int d = 1; d < 64; d *= 2) {
+    const int u = __shfl_up(v, d, 64);
+    if (tid >= d) v += u;
+  }
+  if (tid == 0) off[0] = 0;
+  if (tid < count) off[tid + 1] = v;
 }
 
 // Work item g of a pool launch: the cluster's slot, the workgroup index
@@ -1654,14 +1674,7 @@ __device__ __forceinline__ void pool_force_body(const PoolSlot* __restrict__ slo
     s_n[tid] = (sc->done || sc->n_act <= 0) ? 0 : sc->plan.items;
   }
   __syncthreads();
-  if (tid == 0) {
-    int acc = 0;
-    for (int k = 0; k < count; ++k) {
-      s_off[k] = acc;
-      acc += s_n[k];
-    }
-    s_off[count] = acc;
-  }
+  pool_offsets(s_n, count, s_off);
   __syncthreads();
   const int total = s_off[count];
   for (int g = blockIdx.x; g < total; g += gridDim.x) {
@@ -1700,14 +1713,7 @@ __global__ __launch_bounds__(kBlock) void k_pool_correct(const PoolSlot* __restr
     s_n[tid] = blocks;
   }
   __syncthreads();
-  if (tid == 0) {
-    int acc = 0;
-    for (int k = 0; k < count; ++k) {
-      s_off[k] = acc;
-      acc += s_n[k];
-    }
-    s_off[count] = acc;
-  }
+  pool_offsets(s_n, count, s_off);
   __syncthreads();
   const int total = s_off[count];
   for (int g = blockIdx.x; g < total; g += gridDim.x) {
