@@ -208,7 +208,7 @@ def main():
     ap.add_argument("--requests", type=int, default=512, help="serving: number of clusters")
     ap.add_argument("--rho", type=float, default=1.0,
                     help="serving: arrival rate as a multiple of the sequential solve rate")
-    ap.add_argument("--max-clusters", type=int, default=64, help="serving: pool slots")
+    ap.add_argument("--max-clusters", type=int, default=256, help="serving: pool slots")
     ap.add_argument("--plan-sweep", action="store_true",
                     help="time the force kernel of the workload's sphere for a range of block sizes, with "
                          "gd_force's own decomposition and with every forced one (gd_force_plan); one JSON "

@@ -309,7 +309,7 @@ gd_status gd_set_state(gd_ctx* c, const double* x, const double* v, const double
 typedef struct gd_pool gd_pool;
 
 /* Arena bytes for max_clusters slots plus the workspaces of `count` clusters
- * of sizes n[0..count) resident at once (host-only). max_clusters <= 64. */
+ * of sizes n[0..count) resident at once (host-only). max_clusters <= 256. */
 gd_status gd_pool_arena_bytes(int32_t max_clusters, const int64_t* n, int32_t count, size_t* bytes);
 
 /* Create an empty pool. p: parameters shared by every cluster (bh_index -1,

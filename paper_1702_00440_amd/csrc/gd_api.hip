@@ -1131,6 +1131,7 @@ struct gd_pool {
   PoolSlot* d_slots = nullptr;
   PoolTable* d_tab = nullptr;
   PoolStatus* d_status = nullptr;
+  PoolWork* d_work = nullptr;
   PoolStatus* h_status = nullptr;  // pinned
   PoolTable* h_tab = nullptr;      // pinned staging
   PoolSlot* h_slot = nullptr;      // pinned staging
@@ -1153,7 +1154,7 @@ namespace {
 
 size_t pool_table_bytes(int max_clusters) {
   return align_up(sizeof(PoolSlot) * (size_t)max_clusters) + align_up(sizeof(PoolTable)) +
-         align_up(sizeof(PoolStatus) * (size_t)max_clusters);
+         align_up(sizeof(PoolStatus) * (size_t)max_clusters) + align_up(sizeof(PoolWork));
 }
 
 // First-fit placement of `bytes` in the arena heap, between the blocks of the
@@ -1210,7 +1211,8 @@ gd_status pool_build_graph(gd_pool* P) {
                 "begin capture"));
   hipError_t e = hipSuccess;
   for (int k = 0; k < kPoolSteps && e == hipSuccess; ++k)
-    e = launch_pool_step(P->d_slots, P->d_tab, (P->p.flags & GD_FLAG_MIXED) != 0, P->capture_stream);
+    e = launch_pool_step(P->d_slots, P->d_tab, P->d_work, (P->p.flags & GD_FLAG_MIXED) != 0,
+                         P->capture_stream);
   if (e == hipSuccess) e = launch_pool_status(P->d_slots, P->d_tab, P->d_status, P->capture_stream);
   hipError_t e2 = hipStreamEndCapture(P->capture_stream, &g);
   if (e != hipSuccess || e2 != hipSuccess) {
@@ -1247,7 +1249,7 @@ gd_status gd_pool_create(gd_pool** out, const gd_params* p, int32_t max_clusters
     return st;
   };
   if (!p || !arena) return bad(GD_EINVAL, "NULL argument");
-  if (max_clusters < 1 || max_clusters > kMaxPool) return bad(GD_EINVAL, "max_clusters must be in [1, 64]");
+  if (max_clusters < 1 || max_clusters > kMaxPool) return bad(GD_EINVAL, "max_clusters must be in [1, 256]");
   int kmax = 0;
   if (const char* why = check_params(p, 2, &kmax)) return bad(GD_EINVAL, why);
   if (p->bh_index != -1 || !(p->eps > 0.0))
@@ -1270,6 +1272,8 @@ gd_status gd_pool_create(gd_pool** out, const gd_params* p, int32_t max_clusters
   off += align_up(sizeof(PoolTable));
   P->d_status = (PoolStatus*)(P->arena + off);
   off += align_up(sizeof(PoolStatus) * (size_t)max_clusters);
+  P->d_work = (PoolWork*)(P->arena + off);
+  off += align_up(sizeof(PoolWork));
   P->heap_off = off;
   gd_status st = GD_OK;
   if (st == GD_OK) st = P->hip(hipHostMalloc((void**)&P->h_status, sizeof(PoolStatus) * max_clusters, 0), "pinned status");

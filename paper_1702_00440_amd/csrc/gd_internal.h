@@ -281,7 +281,7 @@ inline void launch_grids(int n, int ipl, int* force_grid, int* correct_grid) {
 // resident cluster by one of its own block steps, with one launch per phase
 // (predict, force, correct) for all of them. The tables live in device memory
 // at the head of the pool's arena.
-constexpr int kMaxPool = 64;
+constexpr int kMaxPool = 256;
 
 struct PoolSlot {
   Dev d;
@@ -294,13 +294,22 @@ struct PoolTable {
   int pred_off[kMaxPool + 1];  // prefix sum of the clusters' predictor blocks
 };
 
+// Work of each resident cluster in the current pool step (by table
+// position), written by the pool predictor for the force and corrector
+// launches: force items, corrector workgroups (0 once the cluster is done).
+struct PoolWork {
+  int force_n[kMaxPool];
+  int correct_n[kMaxPool];
+};
+
 // Per-slot status gathered after each batch of pool steps.
 struct PoolStatus {
   long long t_now, block_steps, particle_steps, pairs, clamps;
   int done, nonfinite;
 };
 
-hipError_t launch_pool_step(const PoolSlot* slots, const PoolTable* tab, bool mixed, hipStream_t s);
+hipError_t launch_pool_step(const PoolSlot* slots, const PoolTable* tab, PoolWork* work, bool mixed,
+                            hipStream_t s);
 // Lagrange radii of the ascending fractions frac[0..n_frac) into out[0..n_frac),
 // Eq. (5) into out[n_frac], the half-mass radius into out[n_frac + 1].
 hipError_t launch_diagnostics(const Dev& d, const Consts& c, const double* frac, int n_frac,

@@ -1188,8 +1188,11 @@ __global__ __launch_bounds__(kBlock) void k_reduce_out(Dev d, Consts c, double* 
 // with their predicted state (for the force kernel) and their a, jerk and
 // level (for the corrector), stored by list position.
 
+// work_items / work_blocks (pool predictor, may be NULL): the cluster's force
+// items and corrector workgroups for this step, written by its workgroup 0.
 __device__ __forceinline__ void predict_body(const Dev& d, const Consts& c, int mode,
-                                             double t_explicit, int blk) {
+                                             double t_explicit, int blk, int* work_items = nullptr,
+                                             int* work_blocks = nullptr) {
   Sched* __restrict__ sc = d.sc;
   const int n = c.n, kmax = c.kmax;
   __shared__ long long s_tnext;
@@ -1229,6 +1232,12 @@ __device__ __forceinline__ void predict_body(const Dev& d, const Consts& c, int 
         sc->n_act = nact;
         sc->done = done;
         if (nact > 0) sc->plan = pl;
+        if (work_items) {
+          const bool w = !done && nact > 0;
+          const int per_wg = w ? kBlock / correct_lanes(pl.s) : 1;
+          *work_items = w ? pl.items : 0;
+          *work_blocks = w ? (nact + per_wg - 1) / per_wg : 0;
+        }
       }
     }
   }
@@ -1600,31 +1609,42 @@ __global__ void k_set_state(Sched* __restrict__ sc, int n, int kmax, double dt_m
 
 constexpr int kPoolGrid = 1024;
 
-static_assert(kMaxPool <= 64, "one wave holds the table of a pool launch");
+static_assert(kMaxPool <= kBlock, "one thread per resident cluster loads its record");
 
 // The last entry k with off[k] <= g (count entries, off in LDS, off[0] = 0,
 // non-decreasing: clusters without work have equal offsets), by the whole
-// wave in one step: lane l tests entry l + 1, and k is the number that pass.
-// Every lane of the wave must be active.
+// wave: lane l tests entries l + 1, l + 65, ..., and k is the number that
+// pass. Every lane of the wave must be active.
 __device__ __forceinline__ int pool_find(const int* off, int count, int g) {
-  const int e = (threadIdx.x & 63) + 1;
-  return __popcll(__ballot(e < count && off[e] <= g));
+  int k = 0;
+  for (int base = 1; base < count; base += 64) {
+    const int e = base + (threadIdx.x & 63);
+    k += __popcll(__ballot(e < count && off[e] <= g));
+  }
+  return k;
 }
 
-// off[k] = n[0] + ... + n[k - 1] for k = 0..count (count <= 64, arrays in
-// LDS), by the first wave: an inclusive scan of n across its lanes. The
-// caller synchronises the workgroup before and after.
+// off[k] = n[0] + ... + n[k - 1] for k = 0..count (arrays in LDS), by the
+// first wave: inclusive scans of n across its lanes, 64 entries at a time
+// with the carry of the ones before. The caller synchronises the workgroup
+// before and after.
 __device__ __forceinline__ void pool_offsets(const int* n, int count, int* off) {
   const int tid = threadIdx.x;
   if (tid >= 64) return;
-  int v = tid < count ? n[tid] : 0;
-#pragma unroll
-  for (int d = 1; d < 64; d *= 2) {
-    const int u = __shfl_up(v, d, 64);
-    if (tid >= d) v += u;
-  }
   if (tid == 0) off[0] = 0;
-  if (tid < count) off[tid + 1] = v;
+  int carry = 0;
+  for (int base = 0; base < count; base += 64) {
+    const int e = base + tid;
+    int v = e < count ? n[e] : 0;
+#pragma unroll
+    for (int d = 1; d < 64; d *= 2) {
+      const int u = __shfl_up(v, d, 64);
+      if (tid >= d) v += u;
+    }
+    v += carry;
+    if (e < count) off[e + 1] = v;
+    carry = __shfl(v, 63, 64);
+  }
 }
 
 // Work item g of a pool launch: the cluster's slot, the workgroup index
@@ -1632,46 +1652,49 @@ __device__ __forceinline__ void pool_offsets(const int* n, int count, int* off) 
 // same in every lane; read back from lane 0 so that the slot's record is
 // read with scalar loads and the cluster's loops stay scalar.
 struct PoolItem {
-  int slot, blk, nblk;
+  int k, slot, blk, nblk;  // k: position in the table
 };
 
 __device__ __forceinline__ PoolItem pool_item(const int* off, const int* order, const int* n, int count,
                                               int g) {
   const int k = __builtin_amdgcn_readfirstlane(pool_find(off, count, g));
   PoolItem it;
+  it.k = k;
   it.slot = __builtin_amdgcn_readfirstlane(order[k]);
   it.blk = g - __builtin_amdgcn_readfirstlane(off[k]);
   it.nblk = n ? __builtin_amdgcn_readfirstlane(n[k]) : 0;
   return it;
 }
 
+// The table is read whole (entries past count are in bounds and unused), so
+// that its loads do not wait for the count.
 __global__ __launch_bounds__(kBlock) void k_pool_predict(const PoolSlot* __restrict__ slots,
-                                                         const PoolTable* __restrict__ tab) {
+                                                         const PoolTable* __restrict__ tab,
+                                                         PoolWork* __restrict__ work) {
   __shared__ int s_off[kMaxPool + 1], s_order[kMaxPool];
   const int tid = threadIdx.x;
   const int count = tab->count;
-  if (tid <= count) s_off[tid] = tab->pred_off[tid];
-  if (tid < count) s_order[tid] = tab->order[tid];
+  for (int k = tid; k <= kMaxPool; k += kBlock) s_off[k] = tab->pred_off[k];
+  for (int k = tid; k < kMaxPool; k += kBlock) s_order[k] = tab->order[k];
   __syncthreads();
   const int total = s_off[count];
   for (int g = blockIdx.x; g < total; g += gridDim.x) {
     const PoolItem it = pool_item(s_off, s_order, nullptr, count, g);
     const PoolSlot& ps = slots[it.slot];
-    predict_body(ps.d, ps.c, kPredAuto, 0.0, it.blk);
+    predict_body(ps.d, ps.c, kPredAuto, 0.0, it.blk, &work->force_n[it.k], &work->correct_n[it.k]);
   }
 }
 
 template <bool kMixed>
 __device__ __forceinline__ void pool_force_body(const PoolSlot* __restrict__ slots,
-                                                const PoolTable* __restrict__ tab) {
+                                                const PoolTable* __restrict__ tab,
+                                                const PoolWork* __restrict__ work) {
   __shared__ int s_off[kMaxPool + 1], s_order[kMaxPool], s_n[kMaxPool];
   const int tid = threadIdx.x;
   const int count = tab->count;
-  if (tid < count) {
-    const int sl = tab->order[tid];
-    const Sched* sc = slots[sl].d.sc;
-    s_order[tid] = sl;
-    s_n[tid] = (sc->done || sc->n_act <= 0) ? 0 : sc->plan.items;
+  for (int k = tid; k < kMaxPool; k += kBlock) {
+    s_order[k] = tab->order[k];
+    s_n[k] = work->force_n[k];
   }
   __syncthreads();
   pool_offsets(s_n, count, s_off);
@@ -1687,30 +1710,24 @@ __device__ __forceinline__ void pool_force_body(const PoolSlot* __restrict__ slo
 // Both variants fit 128 VGPRs (4 waves per SIMD) without spills, once the
 // cluster's record is read with scalar loads (pool_item).
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_pool_force(
-    const PoolSlot* __restrict__ slots, const PoolTable* __restrict__ tab) {
-  pool_force_body<false>(slots, tab);
+    const PoolSlot* __restrict__ slots, const PoolTable* __restrict__ tab, const PoolWork* __restrict__ work) {
+  pool_force_body<false>(slots, tab, work);
 }
 
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_pool_force_mixed(
-    const PoolSlot* __restrict__ slots, const PoolTable* __restrict__ tab) {
-  pool_force_body<true>(slots, tab);
+    const PoolSlot* __restrict__ slots, const PoolTable* __restrict__ tab, const PoolWork* __restrict__ work) {
+  pool_force_body<true>(slots, tab, work);
 }
 
 __global__ __launch_bounds__(kBlock) void k_pool_correct(const PoolSlot* __restrict__ slots,
-                                                         const PoolTable* __restrict__ tab) {
+                                                         const PoolTable* __restrict__ tab,
+                                                         const PoolWork* __restrict__ work) {
   __shared__ int s_off[kMaxPool + 1], s_order[kMaxPool], s_n[kMaxPool];
   const int tid = threadIdx.x;
   const int count = tab->count;
-  if (tid < count) {
-    const int sl = tab->order[tid];
-    const Sched* sc = slots[sl].d.sc;
-    s_order[tid] = sl;
-    int blocks = 0;
-    if (!sc->done && sc->n_act > 0) {
-      const int per_wg = kBlock / correct_lanes(sc->plan.s);
-      blocks = (sc->n_act + per_wg - 1) / per_wg;
-    }
-    s_n[tid] = blocks;
+  for (int k = tid; k < kMaxPool; k += kBlock) {
+    s_order[k] = tab->order[k];
+    s_n[k] = work->correct_n[k];
   }
   __syncthreads();
   pool_offsets(s_n, count, s_off);
@@ -2038,17 +2055,19 @@ hipError_t launch_diagnostics(const Dev& d, const Consts& c, const double* frac,
   return hipGetLastError();
 }
 
-hipError_t launch_pool_step(const PoolSlot* slots, const PoolTable* tab, bool mixed, hipStream_t s) {
-  hipLaunchKernelGGL(k_pool_predict, dim3(kPoolGrid), dim3(kBlock), 0, s, slots, tab);
+hipError_t launch_pool_step(const PoolSlot* slots, const PoolTable* tab, PoolWork* work, bool mixed,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_pool_predict, dim3(kPoolGrid), dim3(kBlock), 0, s, slots, tab, work);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  const PoolWork* cw = work;
   if (mixed)
-    hipLaunchKernelGGL(k_pool_force_mixed, dim3(kPoolGrid), dim3(kBlock), 0, s, slots, tab);
+    hipLaunchKernelGGL(k_pool_force_mixed, dim3(kPoolGrid), dim3(kBlock), 0, s, slots, tab, cw);
   else
-    hipLaunchKernelGGL(k_pool_force, dim3(kPoolGrid), dim3(kBlock), 0, s, slots, tab);
+    hipLaunchKernelGGL(k_pool_force, dim3(kPoolGrid), dim3(kBlock), 0, s, slots, tab, cw);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_pool_correct, dim3(kPoolGrid), dim3(kBlock), 0, s, slots, tab);
+  hipLaunchKernelGGL(k_pool_correct, dim3(kPoolGrid), dim3(kBlock), 0, s, slots, tab, cw);
   return hipGetLastError();
 }
 

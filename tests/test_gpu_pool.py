@@ -44,6 +44,36 @@ def _drain(pool):
     return done
 
 
+def test_pool_of_more_than_one_wave_of_clusters():
+    """A pool of 150 resident clusters (more than one 64-lane wave of table
+    entries in the kernels' cluster search and work prefix sums), N from 64
+    to 400, to t = 0.125: every cluster finishes, and 12 of them, spread over
+    the table, are bitwise the same as alone."""
+    rng = np.random.default_rng(5)
+    sizes = [(int(rng.integers(64, 401)), 3000 + k) for k in range(150)]
+    t_end = 0.125
+    p = g.make_params(**PARAMS)
+    arena = torch.empty(g.gd_pool_arena_bytes(150, [n for n, _ in sizes]), dtype=torch.uint8, device=DEV)
+    pool = g.gd_pool_create(p, 150, arena)
+    slots = {}
+    for n, seed in sizes:
+        m, x, v = _ics(n, seed)
+        slots[g.gd_pool_admit(pool, m, x, v, t_end)] = (n, seed)
+    assert g.gd_pool_resident(pool) == 150
+    finished = _drain(pool)
+    assert sorted(finished) == sorted(slots)
+    for sl in sorted(slots)[::13]:
+        n, seed = slots[sl]
+        xo = torch.empty(n, 3, dtype=torch.float64, device=DEV)
+        vo = torch.empty_like(xo)
+        st = g.gd_pool_result(pool, sl, xo, vo)
+        xa, va, sa = _alone(n, seed, t_end)
+        np.testing.assert_array_equal(host(xo), xa)
+        np.testing.assert_array_equal(host(vo), va)
+        assert st["block_steps"] == sa["block_steps"] and st["e"] == sa["e"]
+    g.gd_pool_destroy(pool)
+
+
 def test_pool_results_equal_alone_bitwise():
     sizes = [(256, 11), (700, 12), (1024, 13), (2048, 14), (333, 15)]
     t_end = 0.25

@@ -167,7 +167,7 @@ def test_pool_create_validation_host_only():
     lib = g.library()
     pool = C.c_void_p()
     dummy = C.c_void_p(256)
-    for kw, mc in [(dict(), 0), (dict(), 65), (dict(eps=0.0), 4), (dict(bh_index=1, eps_bh=1e-6), 4)]:
+    for kw, mc in [(dict(), 0), (dict(), 257), (dict(eps=0.0), 4), (dict(bh_index=1, eps_bh=1e-6), 4)]:
         p = g.make_params(**kw)
         rc = lib.gd_pool_create(C.byref(pool), C.byref(p), mc, dummy, 1 << 30, None)
         assert rc == g.GD_EINVAL, (kw, mc)
