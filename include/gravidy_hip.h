@@ -308,8 +308,12 @@ gd_status gd_set_state(gd_ctx* c, const double* x, const double* v, const double
  */
 typedef struct gd_pool gd_pool;
 
+/* Largest max_clusters of a pool. */
+#define GD_POOL_MAX_CLUSTERS 256
+
 /* Arena bytes for max_clusters slots plus the workspaces of `count` clusters
- * of sizes n[0..count) resident at once (host-only). max_clusters <= 256. */
+ * of sizes n[0..count) resident at once (host-only). max_clusters <=
+ * GD_POOL_MAX_CLUSTERS. */
 gd_status gd_pool_arena_bytes(int32_t max_clusters, const int64_t* n, int32_t count, size_t* bytes);
 
 /* Create an empty pool. p: parameters shared by every cluster (bh_index -1,
@@ -330,7 +334,8 @@ gd_status gd_pool_admit(gd_pool* pool, int64_t n, const double* m, const double*
 /* Advance every resident cluster by up to 32 of its own block steps (one
  * graph replay). Clusters that reached their end time (or produced a
  * non-finite force) stop being resident; their slots are written to
- * finished (host, capacity 64, may be NULL) and counted in *n_finished.
+ * finished (host, room for the pool's max_clusters entries, may be NULL)
+ * and counted in *n_finished.
  * Synchronises. */
 gd_status gd_pool_run(gd_pool* pool, int32_t* finished, int32_t* n_finished);
 

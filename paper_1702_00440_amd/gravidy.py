@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libgravidy_hip.so")
 
 GD_OK, GD_EINVAL, GD_ENOMEM, GD_EHIP, GD_ESTATE, GD_ENONFINITE = 0, -1, -2, -3, -4, -5
 GD_FLAG_MIXED = 1
+GD_POOL_MAX_CLUSTERS = 256
 _NAMES = {GD_EINVAL: "GD_EINVAL", GD_ENOMEM: "GD_ENOMEM", GD_EHIP: "GD_EHIP",
           GD_ESTATE: "GD_ESTATE", GD_ENONFINITE: "GD_ENONFINITE"}
 
@@ -357,7 +358,7 @@ def gd_pool_admit(pool, m, x, v, t_end: float):
 
 
 def gd_pool_run(pool) -> list:
-    fin = (C.c_int32 * 64)()
+    fin = (C.c_int32 * GD_POOL_MAX_CLUSTERS)()
     nf = C.c_int32(0)
     _check_pool(library().gd_pool_run(pool, fin, C.byref(nf)), pool)
     return [int(fin[k]) for k in range(nf.value)]

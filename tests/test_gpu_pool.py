@@ -44,6 +44,27 @@ def _drain(pool):
     return done
 
 
+def test_pool_run_reports_more_than_64_finished_at_once():
+    """With dt_min = dt_max every cluster reaches t = dt_max in one block step,
+    so all 100 clusters of a 128-slot pool finish in the first replay: one
+    gd_pool_run reports all of them (the finished list holds the pool's
+    max_clusters entries)."""
+    p = g.make_params(eta=0.01, eps=1e-4, dt_max=0.125, dt_min=0.125)
+    sizes = [(32 + (k % 7), 5000 + k) for k in range(100)]
+    arena = torch.empty(g.gd_pool_arena_bytes(128, [n for n, _ in sizes]), dtype=torch.uint8, device=DEV)
+    pool = g.gd_pool_create(p, 128, arena)
+    slots = set()
+    for n, seed in sizes:
+        m, x, v = _ics(n, seed)
+        slots.add(g.gd_pool_admit(pool, m, x, v, 0.125))
+    finished = g.gd_pool_run(pool)
+    assert sorted(finished) == sorted(slots)
+    assert g.gd_pool_resident(pool) == 0
+    for sl in finished:
+        assert g.gd_pool_result(pool, sl)["block_steps"] == 1
+    g.gd_pool_destroy(pool)
+
+
 def test_pool_of_more_than_one_wave_of_clusters():
     """A pool of 150 resident clusters (more than one 64-lane wave of table
     entries in the kernels' cluster search and work prefix sums), N from 64

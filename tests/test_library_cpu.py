@@ -40,6 +40,17 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, n)
 
 
+def test_binding_constants_match_the_header():
+    """Every #define GD_<NAME> <integer> of the public header has the same
+    value in the binding (buffers the binding sizes from them must hold what
+    the library writes)."""
+    text = open(HEADER).read()
+    found = re.findall(r"#define\s+(GD_[A-Z0-9_]+)\s+(\d+)\b", text)
+    assert len(found) >= 5
+    for name, value in found:
+        assert getattr(g, name) == int(value), name
+
+
 def test_library_has_gfx950_code_object():
     data = open(g.LIB_PATH, "rb").read()
     assert b"gfx950" in data
