@@ -213,8 +213,8 @@ def test_pool_c4_shape_against_oracle():
     oracle's own integration of the same cluster: identical block, particle
     and pair counts and dt_min clamps; energy at t = 0 and t = 0.5 within
     1e-10; final positions within 1e-9; energy drift of each solve within
-    1e-6 per time unit (the bound of the survey's reading of the paper's
-    Sec. 3.2 energy conservation), as the oracle's own is."""
+    1e-6 per time unit (the bound taken for the paper's Sec. 3.2 energy
+    conservation), as the oracle's own is."""
     sizes = _c4_clusters(6)
     assert max(n for n, _ in sizes) > 8000
     res = _run_pool(sizes, 0.5)
