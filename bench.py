@@ -200,7 +200,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the force-launch event timing")
     ap.add_argument("--no-full-force", action="store_true",
-                    help="skip the N = 262144 full-force figures (FP64 and mixed) of the default line")
+                    help="skip the other workloads' figures of the default line (the N = 262144 full force in "
+                         "FP64 and mixed, the 2^20 + 1 central-particle full force, 128-request serving)")
     ap.add_argument("--kernel-hash", action="store_true",
                     help="print the hash of the kernel sources that a counter summary is tied to")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -378,6 +379,10 @@ def main():
     cl.close()
     if not args.no_full_force:
         out["full_force_n262144"] = full_force_imf(1, 3)
+        out["full_force_n1048577_central"] = central_full_force(1)
+        sv = serving_result(128, 1.0, args.max_clusters, False)
+        out["serving_requests128"] = {k: sv[k] for k in ("metric", "value", "unit", "latency_p50_s", "latency_p99_s",
+                                                         "sequential", "pairs_per_s", "failed_requests", "config")}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(out), flush=True)
@@ -578,6 +583,12 @@ def serving_bench(args):
     t = 0.5; Poisson arrivals at rho times the sequential solve rate measured
     first on the same requests. Reports solves/s and latency percentiles for
     the pool and for sequential plain solves."""
+    print(json.dumps(serving_result(args.requests, args.rho, args.max_clusters, args.precision == "mixed")),
+          flush=True)
+
+
+def serving_result(requests, rho, max_clusters, mixed):
+    """The serving measurement of serving_bench as a dict."""
     import numpy as np
     import torch
 
@@ -589,12 +600,11 @@ def serving_bench(args):
     dev = "cuda:0"
     t_end = 0.5
     reqs = []
-    for k in range(args.requests):
+    for k in range(requests):
         n = int(round(np.exp(rng.uniform(np.log(256), np.log(8192)))))
         m, x, v = plummer(n, 1000 + k)
         reqs.append(serving.Request(k, 0.0, torch.as_tensor(m).to(dev), torch.as_tensor(x).to(dev).contiguous(),
                                     torch.as_tensor(v).to(dev).contiguous(), t_end))
-    mixed = args.precision == "mixed"
     p = g.make_params(eta=0.01, eps=1e-4, dt_max=0.125, dt_min=2.0 ** -22,
                       flags=g.GD_FLAG_MIXED if mixed else 0)
     # warm-up: one small solve each way
@@ -604,15 +614,15 @@ def serving_bench(args):
     seq = serving.serve_sequential(p, reqs)
     seq_wall = time.perf_counter() - t0
     seq_rate = len(reqs) / seq_wall
-    lam = args.rho * seq_rate
+    lam = rho * seq_rate
     arr = np.cumsum(rng.exponential(1.0 / lam, len(reqs)))
     arr -= arr[0]
     for r, a in zip(reqs, arr):
         r.arrival = float(a)
-    seq_lat = [r.latency for r in serving.serve_sequential(p, reqs)] if args.rho > 0 else []
+    seq_lat = [r.latency for r in serving.serve_sequential(p, reqs)] if rho > 0 else []
     nmax = max(r.m.shape[0] for r in reqs)
-    arena_bytes = g.gd_pool_arena_bytes(args.max_clusters, [nmax] * args.max_clusters)
-    srv = serving.PoolServer(p, args.max_clusters, arena_bytes)
+    arena_bytes = g.gd_pool_arena_bytes(max_clusters, [nmax] * max_clusters)
+    srv = serving.PoolServer(p, max_clusters, arena_bytes)
     srv.serve(reqs[:2])  # warm-up (graph capture)
     # capacity: every request available at t = 0
     burst = [serving.Request(r.rid, 0.0, r.m, r.x, r.v, r.t_end) for r in reqs]
@@ -637,20 +647,54 @@ def serving_bench(args):
         "vs_baseline": None,
         "dtype": "f32 pair arithmetic, f64 state" if mixed else "f64",
         "data": "synthetic",
-        "config": {"workload": f"serving_plummer_n256-8192_t0.5_{'mixed' if mixed else 'fp64'}", "requests": len(reqs), "rho": args.rho,
-                   "arrival_rate_per_s": lam, "max_clusters": args.max_clusters, "eps": 1e-4, "eta": 0.01},
+        "config": {"workload": f"serving_plummer_n256-8192_t0.5_{'mixed' if mixed else 'fp64'}", "requests": len(reqs), "rho": rho,
+                   "arrival_rate_per_s": lam, "max_clusters": max_clusters, "eps": 1e-4, "eta": 0.01},
         "value_kind": "capacity: all requests queued at t=0",
         "latency_p50_s": float(np.percentile(lat, 50)),
         "latency_p99_s": float(np.percentile(lat, 99)),
-        "latency_kind": f"Poisson arrivals at rho={args.rho} x the sequential solve rate",
+        "latency_kind": f"Poisson arrivals at rho={rho} x the sequential solve rate",
         "pairs_per_s": pairs / wall,
         "sequential": {
             "solves_per_s": seq_rate,
             "latency_p50_s": float(np.percentile(seq_lat, 50)) if seq_lat else None,
             "latency_p99_s": float(np.percentile(seq_lat, 99)) if seq_lat else None,
         },
+        "failed_requests": sum(not r.ok for r in res_burst) + sum(not r.ok for r in res),
     }
-    print(json.dumps(out), flush=True)
+    return out
+
+
+def central_full_force(steps):
+    """One O(N^2) force and jerk evaluation of the central-particle workload
+    (2^20 Plummer stars plus the particle of mass 0.01 at the origin, eps 1e-4,
+    eps_bh 1e-6 for its pairs), in mixed precision: the force launch of
+    gd_reinit timed with its own HIP events, `steps` times; pair interactions
+    per second and the fraction of the FP64 and FP32 vector peaks at 60 flops
+    per pair."""
+    import torch
+
+    from paper_1702_00440_amd import gravidy as g
+    from synth_inputs import WORKLOADS, plummer_with_bh
+
+    w = WORKLOADS["plummer_bh_n1048576"]
+    dev = torch.device("cuda:0")
+    m, x, v = plummer_with_bh(w["n_stars"], w["seed"], m_bh=w["m_bh"])
+    n = m.shape[0]
+    md, xd, vd = (torch.as_tensor(a).to(dev).contiguous() for a in (m, x, v))
+    cl = g.Cluster(m, x, v, eta=w["eta"], eps=w["eps"], dt_max=w["dt_max"], dt_min=w["dt_min"], device=dev,
+                   eps_bh=w["eps_bh"], bh_index=w["n_stars"], flags=g.GD_FLAG_MIXED)
+    g.gd_profile_force(cl.ctx, True)
+    for _ in range(steps):
+        g.gd_reinit(cl.ctx, md, xd, vd)
+    prof = g.gd_profile_get(cl.ctx)
+    cl.close()
+    sec = prof["force_ms"] / 1e3 / prof["launches"]
+    tf = FLOPS_PER_PAIR * n * n / sec / 1e12
+    return {"workload": f"plummer_bh_n{n} full force (N_act = N), mixed, eps 1e-4, eps_bh 1e-6, seed {w['seed']}",
+            "pairs_per_s": n * n / sec, "kernel_ms": sec * 1e3, "launches": prof["launches"],
+            "achieved_tflops": tf, "frac_fp64_peak": tf / PEAK_FP64_VECTOR_TFLOPS,
+            "frac_fp32_peak": tf / PEAK_FP32_VECTOR_TFLOPS,
+            "timing": "HIP events around each force launch (hipExtLaunchKernelGGL), average over launches"}
 
 
 if __name__ == "__main__":
