@@ -294,12 +294,23 @@ struct PoolTable {
   int pred_off[kMaxPool + 1];  // prefix sum of the clusters' predictor blocks
 };
 
+// A cluster's block step as the pool predictor fixed it: block size, block
+// time and decomposition (what the force and corrector otherwise read from
+// the cluster's record).
+struct PoolStep {
+  long long t_next;
+  int n_act;
+  Plan plan;
+};
+
 // Work of each resident cluster in the current pool step (by table
 // position), written by the pool predictor for the force and corrector
-// launches: force items, corrector workgroups (0 once the cluster is done).
+// launches: force items, corrector workgroups (0 once the cluster is done)
+// and the step itself.
 struct PoolWork {
   int force_n[kMaxPool];
   int correct_n[kMaxPool];
+  PoolStep step[kMaxPool];
 };
 
 // Per-slot status gathered after each batch of pool steps.

@@ -617,7 +617,8 @@ __device__ __forceinline__ void finish_item(const Dev& d, const Consts& c, int L
 // the active list of parity par; otherwise that of a step whose predictor ran
 // before (list 0).
 template <bool kMaskSelf, bool kCentral, bool kMixed, int kI, bool kStep = false>
-__device__ __forceinline__ void force_body(const Dev& d, const Consts& c, int blk, int nblk, int par = 0) {
+__device__ __forceinline__ void force_body(const Dev& d, const Consts& c, int blk, int nblk, int par = 0,
+                                           const PoolStep* step = nullptr) {
   Sched* __restrict__ sc = d.sc;
   const int n = c.n;
   const size_t lo = (size_t)par * n;  // list offset
@@ -738,6 +739,11 @@ __device__ __forceinline__ void force_body(const Dev& d, const Consts& c, int bl
       sc->done = 0;
       sc->refill = 0;
     }
+  } else if (step) {
+    // a pool launch: the step as its predictor fixed it (only clusters that
+    // have work get items)
+    n_act = __builtin_amdgcn_readfirstlane(step->n_act);
+    p = uniform_plan(step->plan);
   } else {
     if (__builtin_amdgcn_readfirstlane(sc->done)) return;
     n_act = __builtin_amdgcn_readfirstlane(sc->n_act);
@@ -865,7 +871,8 @@ __device__ __forceinline__ bool finite6(const double f[6]) {
 // did not correct (predict_rest). Otherwise the corrector of a step whose
 // list is list 0.
 template <bool kStep>
-__device__ __forceinline__ void correct_body(const Dev& d, const Consts& c, int blk, int nblk, int par = 0) {
+__device__ __forceinline__ void correct_body(const Dev& d, const Consts& c, int blk, int nblk, int par = 0,
+                                             const PoolStep* step = nullptr) {
   Sched* __restrict__ sc = d.sc;
   const int tid = threadIdx.x;
   const size_t lo = (size_t)par * c.n;  // list offset
@@ -911,11 +918,12 @@ __device__ __forceinline__ void correct_body(const Dev& d, const Consts& c, int 
       return;
     }
   } else {
-    if (sc->done) return;
+    // (a pool launch gives workgroups only to clusters whose step runs)
+    if (!step && sc->done) return;
   }
-  const int n_act = sc->n_act;
-  const long long t_next = sc->t_next;
-  const Plan p = sc->plan;
+  const int n_act = step ? step->n_act : sc->n_act;
+  const long long t_next = step ? step->t_next : sc->t_next;
+  const Plan p = step ? step->plan : sc->plan;
   // speculated next block time (kStep)
   const long long t_spec = kStep ? t_next + (1LL << (c.kmax - sc->fine)) : 0;
   const int kthr_spec = kStep ? max(0, c.kmax - (int)__builtin_ctzll((unsigned long long)t_spec)) : 0;
@@ -1188,11 +1196,11 @@ __global__ __launch_bounds__(kBlock) void k_reduce_out(Dev d, Consts c, double* 
 // with their predicted state (for the force kernel) and their a, jerk and
 // level (for the corrector), stored by list position.
 
-// work_items / work_blocks (pool predictor, may be NULL): the cluster's force
-// items and corrector workgroups for this step, written by its workgroup 0.
+// work (pool predictor, may be NULL): the cluster's force items, corrector
+// workgroups and step for this pool step, written by its workgroup 0 at
+// table position k.
 __device__ __forceinline__ void predict_body(const Dev& d, const Consts& c, int mode,
-                                             double t_explicit, int blk, int* work_items = nullptr,
-                                             int* work_blocks = nullptr) {
+                                             double t_explicit, int blk, PoolWork* work = nullptr, int k = 0) {
   Sched* __restrict__ sc = d.sc;
   const int n = c.n, kmax = c.kmax;
   __shared__ long long s_tnext;
@@ -1232,11 +1240,14 @@ __device__ __forceinline__ void predict_body(const Dev& d, const Consts& c, int 
         sc->n_act = nact;
         sc->done = done;
         if (nact > 0) sc->plan = pl;
-        if (work_items) {
+        if (work) {
           const bool w = !done && nact > 0;
           const int per_wg = w ? kBlock / correct_lanes(pl.s) : 1;
-          *work_items = w ? pl.items : 0;
-          *work_blocks = w ? (nact + per_wg - 1) / per_wg : 0;
+          work->force_n[k] = w ? pl.items : 0;
+          work->correct_n[k] = w ? (nact + per_wg - 1) / per_wg : 0;
+          work->step[k].t_next = t_next;
+          work->step[k].n_act = nact;
+          work->step[k].plan = pl;
         }
       }
     }
@@ -1681,7 +1692,7 @@ __global__ __launch_bounds__(kBlock) void k_pool_predict(const PoolSlot* __restr
   for (int g = blockIdx.x; g < total; g += gridDim.x) {
     const PoolItem it = pool_item(s_off, s_order, nullptr, count, g);
     const PoolSlot& ps = slots[it.slot];
-    predict_body(ps.d, ps.c, kPredAuto, 0.0, it.blk, &work->force_n[it.k], &work->correct_n[it.k]);
+    predict_body(ps.d, ps.c, kPredAuto, 0.0, it.blk, work, it.k);
   }
 }
 
@@ -1703,7 +1714,7 @@ __device__ __forceinline__ void pool_force_body(const PoolSlot* __restrict__ slo
   for (int g = blockIdx.x; g < total; g += gridDim.x) {
     const PoolItem it = pool_item(s_off, s_order, s_n, count, g);
     const PoolSlot& ps = slots[it.slot];
-    force_body<false, false, kMixed, kIPerLane>(ps.d, ps.c, it.blk, it.nblk);
+    force_body<false, false, kMixed, kIPerLane>(ps.d, ps.c, it.blk, it.nblk, 0, &work->step[it.k]);
   }
 }
 
@@ -1736,7 +1747,7 @@ __global__ __launch_bounds__(kBlock) void k_pool_correct(const PoolSlot* __restr
   for (int g = blockIdx.x; g < total; g += gridDim.x) {
     const PoolItem it = pool_item(s_off, s_order, s_n, count, g);
     const PoolSlot& ps = slots[it.slot];
-    correct_body<false>(ps.d, ps.c, it.blk, it.nblk);
+    correct_body<false>(ps.d, ps.c, it.blk, it.nblk, 0, &work->step[it.k]);
   }
 }
 
