@@ -261,6 +261,16 @@ __device__ __forceinline__ void taylor6(double dt, double x0, double y0, double 
   o[5] = fma(dt, fma(h2, jz0, az0), vz0);
 }
 
+// Uses a value on a path that otherwise ignores it (an empty asm that takes
+// it in a register). A load whose only uses lie past an early-exit branch
+// would otherwise be moved below that branch, into a second round trip after
+// the one that decides the branch; held on the exit path, it stays above and
+// travels with the branch's own loads.
+template <typename T>
+__device__ __forceinline__ void hold(const T& v) {
+  asm volatile("" ::"v"(v));
+}
+
 struct NextStep {
   long long t_next;
   int kthr, n_act, done;
@@ -901,31 +911,49 @@ __device__ __forceinline__ void correct_body(const Dev& d, const Consts& c, int 
     j0[0] = d.ijx[lo + k1]; j0[1] = d.ijy[lo + k1]; j0[2] = d.ijz[lo + k1];
     xp[0] = d.ix[lo + k1]; xp[1] = d.iy[lo + k1]; xp[2] = d.iz[lo + k1];
     vp[0] = d.ivx[lo + k1]; vp[1] = d.ivy[lo + k1]; vp[2] = d.ivz[lo + k1];
-    if (one_slot && r1 < c.s1) {
-      const double* o = d.part + (size_t)k1 * c.s1 + r1;
+    if (one_slot) {
+      // (lanes past the slices read the last one; their sums are not used)
+      const double* o = d.part + (size_t)k1 * c.s1 + min(r1, c.s1 - 1);
 #pragma unroll
       for (int q = 0; q < 6; ++q) g1[q] = o[q * c.part_cs];
     }
   }
 
+  int n_act, fine = 0;
+  long long t_next;
+  Plan p;
   if constexpr (kStep) {
-    if (sc->done || sc->refill) {
+    // every field the step needs in one round trip, with the loads above
+    // (both flags read: no short-circuit load after the first)
+    const int done = sc->done, refill = sc->refill;
+    n_act = sc->n_act;
+    t_next = sc->t_next;
+    p = sc->plan;
+    fine = sc->fine;
+    if (done | refill) {
+      hold(i); hold(lv);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) { hold(a0[q]); hold(j0[q]); hold(xp[q]); hold(vp[q]); }
+#pragma unroll
+      for (int q = 0; q < 6; ++q) hold(g1[q]);
+      hold(n_act); hold(t_next); hold(fine);
+      hold(p.lj); hold(p.it); hold(p.nit); hold(p.s); hold(p.len); hold(p.items);
       // the list this step's corrector would have built next stays free
       if (blk == 0 && tid == 0) {
         sc->lcnt[par] = 0;
-        if (sc->refill) atomicAdd((unsigned long long*)&sc->refills, 1ULL);
+        if (refill) atomicAdd((unsigned long long*)&sc->refills, 1ULL);
       }
       return;
     }
   } else {
     // (a pool launch gives workgroups only to clusters whose step runs)
     if (!step && sc->done) return;
+    n_act = step ? step->n_act : sc->n_act;
+    t_next = step ? step->t_next : sc->t_next;
+    p = step ? step->plan : sc->plan;
   }
-  const int n_act = step ? step->n_act : sc->n_act;
-  const long long t_next = step ? step->t_next : sc->t_next;
-  const Plan p = step ? step->plan : sc->plan;
   // speculated next block time (kStep)
-  const long long t_spec = kStep ? t_next + (1LL << (c.kmax - sc->fine)) : 0;
+  const long long t_spec = kStep ? t_next + (1LL << (c.kmax - fine)) : 0;
   const int kthr_spec = kStep ? max(0, c.kmax - (int)__builtin_ctzll((unsigned long long)t_spec)) : 0;
   const int L = correct_lanes(p.s);
   const int per_wg = kBlock / L;
@@ -1052,12 +1080,19 @@ __device__ __forceinline__ void predict_rest(const Dev& d, const Consts& c, int 
   const int n = c.n, tid = threadIdx.x;
   const int nb = (n + kBlock - 1) / kBlock;
   if (blk >= nb) return;
-  // The first block's state is requested before the schedule record is read.
+  // The first block's state is requested with the schedule record.
   PState ps = load_pstate(d, min(blk * kBlock + tid, n - 1));
   long long tg = d.tag[(size_t)par * n + min(blk * kBlock + tid, n - 1)];
-  if (sc->done || sc->refill) return;
+  const int stop = sc->done | sc->refill;
   const long long t_next = sc->t_next;
-  const long long t_spec = t_next + (1LL << (c.kmax - sc->fine));
+  const int fine = sc->fine;
+  if (stop) {
+    hold(ps.x); hold(ps.y); hold(ps.z); hold(ps.vx); hold(ps.vy); hold(ps.vz);
+    hold(ps.ax); hold(ps.ay); hold(ps.az); hold(ps.jx); hold(ps.jy); hold(ps.jz);
+    hold(ps.tick); hold(ps.lev); hold(tg); hold(t_next); hold(fine);
+    return;
+  }
+  const long long t_spec = t_next + (1LL << (c.kmax - fine));
   const int kthr_spec = max(0, c.kmax - (int)__builtin_ctzll((unsigned long long)t_spec));
   for (int b = blk; b < nb; b += nblk) {
     if (b != blk) {
@@ -1087,7 +1122,41 @@ __global__ __launch_bounds__(kBlock) void k_correct(Dev d, Consts c) {
 // are the longer path (every particle's state, the list counter's round
 // trip), and workgroups start in index order (same-box timing of the
 // N = 16384 integration: 548 ms this way, 563 ms the other way round).
-__global__ __launch_bounds__(kBlock) void k_step_correct(Dev d, Consts c, int par) {
+// k_step_correct's view of a context's arrays: the first array of each group
+// that the workspace layout places one stride apart (the state x .. jz, the j
+// stream px .. pvz, the list arrays ix .. ijz), expanded in the kernel. Passing
+// 41 pointers left the kernel short of scalar registers: their loads came in
+// dependent batches and many were spilled to vector lanes.
+struct DevC {
+  Sched* sc;
+  double *m, *jm, *st, *pj, *il, *part;
+  long long* tick;
+  unsigned char* lev;
+  int *active, *ilev;
+  long long* tag;
+  long long sn, sl;  // strides in doubles: state and j stream; list arrays
+};
+
+__device__ __forceinline__ Dev expand(const DevC& e) {
+  Dev d{};
+  d.sc = e.sc; d.m = e.m; d.jm = e.jm;
+  d.x = e.st; d.y = e.st + e.sn; d.z = e.st + 2 * e.sn;
+  d.vx = e.st + 3 * e.sn; d.vy = e.st + 4 * e.sn; d.vz = e.st + 5 * e.sn;
+  d.ax = e.st + 6 * e.sn; d.ay = e.st + 7 * e.sn; d.az = e.st + 8 * e.sn;
+  d.jx = e.st + 9 * e.sn; d.jy = e.st + 10 * e.sn; d.jz = e.st + 11 * e.sn;
+  d.px = e.pj; d.py = e.pj + e.sn; d.pz = e.pj + 2 * e.sn;
+  d.pvx = e.pj + 3 * e.sn; d.pvy = e.pj + 4 * e.sn; d.pvz = e.pj + 5 * e.sn;
+  d.ix = e.il; d.iy = e.il + e.sl; d.iz = e.il + 2 * e.sl;
+  d.ivx = e.il + 3 * e.sl; d.ivy = e.il + 4 * e.sl; d.ivz = e.il + 5 * e.sl;
+  d.iax = e.il + 6 * e.sl; d.iay = e.il + 7 * e.sl; d.iaz = e.il + 8 * e.sl;
+  d.ijx = e.il + 9 * e.sl; d.ijy = e.il + 10 * e.sl; d.ijz = e.il + 11 * e.sl;
+  d.tick = e.tick; d.lev = e.lev; d.active = e.active; d.ilev = e.ilev; d.tag = e.tag;
+  d.part = e.part;
+  return d;
+}
+
+__global__ __launch_bounds__(kBlock) void k_step_correct(DevC dc, Consts c, int par) {
+  const Dev d = expand(dc);
   const int nb = (c.n + kBlock - 1) / kBlock;
   if ((int)blockIdx.x < nb)
     predict_rest(d, c, blockIdx.x, nb, par);
@@ -1953,7 +2022,19 @@ hipError_t launch_step_force(const Dev& d, const Consts& c, int par, hipStream_t
 }
 
 hipError_t launch_step_correct(const Dev& d, const Consts& c, int par, hipStream_t s) {
-  hipLaunchKernelGGL(k_step_correct, dim3(c.correct_grid + grid_for(c.n)), dim3(kBlock), 0, s, d, c, par);
+  DevC e{};
+  e.sc = d.sc; e.m = d.m; e.jm = d.jm; e.st = d.x; e.pj = d.px; e.il = d.ix; e.part = d.part;
+  e.tick = d.tick; e.lev = d.lev; e.active = d.active; e.ilev = d.ilev; e.tag = d.tag;
+  e.sn = d.y - d.x;
+  e.sl = d.iy - d.ix;
+  // (make_layout places each group one stride apart; any other layout is refused)
+  const double* st[12] = {d.x, d.y, d.z, d.vx, d.vy, d.vz, d.ax, d.ay, d.az, d.jx, d.jy, d.jz};
+  const double* pj[6] = {d.px, d.py, d.pz, d.pvx, d.pvy, d.pvz};
+  const double* il[12] = {d.ix, d.iy, d.iz, d.ivx, d.ivy, d.ivz, d.iax, d.iay, d.iaz, d.ijx, d.ijy, d.ijz};
+  for (int k = 0; k < 12; ++k)
+    if (st[k] != d.x + k * e.sn || il[k] != d.ix + k * e.sl || (k < 6 && pj[k] != d.px + k * e.sn))
+      return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_step_correct, dim3(c.correct_grid + grid_for(c.n)), dim3(kBlock), 0, s, e, c, par);
   return hipGetLastError();
 }
 
