@@ -143,6 +143,24 @@ def _ptr(t, dtype, shape=None, name="array"):
     return t.data_ptr()
 
 
+# One int32 element per device whose address stands for an empty index list:
+# an empty tensor has no storage (its data pointer is NULL), and the C ABI
+# reads a NULL index list as "the current active set". With n_act = 0 the
+# library never reads through the pointer.
+_EMPTY_LIST = {}
+
+
+def _list_ptr(idx, name="idx"):
+    """Device pointer of an int32 index list; an empty list gets a non-NULL address."""
+    p = _ptr(idx, torch.int32, None, name)
+    if idx is not None and idx.numel() == 0 and not p:
+        key = idx.device
+        if key not in _EMPTY_LIST:
+            _EMPTY_LIST[key] = torch.zeros(1, dtype=torch.int32, device=key)
+        p = _EMPTY_LIST[key].data_ptr()
+    return p
+
+
 def _stream_handle(stream=None) -> int:
     s = stream if stream is not None else torch.cuda.current_stream()
     return s.cuda_stream
@@ -212,7 +230,7 @@ def gd_predict(ctx, t: float | None = None) -> None:
 
 def gd_force(ctx, idx=None, acc=None, jerk=None) -> None:
     n_act = 0 if idx is None else idx.shape[0]
-    _check(library().gd_force(ctx, _ptr(idx, torch.int32, None, "idx"), n_act,
+    _check(library().gd_force(ctx, _list_ptr(idx), n_act,
                               _ptr(acc, torch.float64, None, "acc"), _ptr(jerk, torch.float64, None, "jerk")), ctx)
 
 
@@ -220,7 +238,7 @@ def gd_force_plan(ctx, idx, lanes_per_i: int, slices: int, acc=None, jerk=None) 
     """gd_force of an index list with a chosen decomposition of the force
     kernel (lanes per listed particle, j slices)."""
     n_act = idx.shape[0]
-    _check(library().gd_force_plan(ctx, _ptr(idx, torch.int32, None, "idx"), n_act, int(lanes_per_i),
+    _check(library().gd_force_plan(ctx, _list_ptr(idx), n_act, int(lanes_per_i),
                                    int(slices), _ptr(acc, torch.float64, None, "acc"),
                                    _ptr(jerk, torch.float64, None, "jerk")), ctx)
 

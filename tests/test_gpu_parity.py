@@ -44,6 +44,32 @@ def test_initial_force_all_particles(n, seed):
     cl.close()
 
 
+def test_empty_index_list():
+    """An empty index list is an explicit list of no particles: it succeeds and
+    computes nothing, after an explicit-time prediction and after an automatic
+    one (where no list at all would mean the active set, and gd_correct then
+    still needs that set's forces). A list that follows is unaffected."""
+    n = 1000
+    m, x, v = plummer(n, 3)
+    cl = g.Cluster(m, x, v, eta=ETA, eps=EPS, dt_max=DTMAX, dt_min=DTMIN, device=DEV)
+    empty = torch.empty(0, dtype=torch.int32, device=DEV)
+    out_a = torch.empty(0, 3, dtype=torch.float64, device=DEV)
+    out_j = torch.empty(0, 3, dtype=torch.float64, device=DEV)
+    g.gd_predict(cl.ctx, 0.0)
+    g.gd_force(cl.ctx, empty, out_a, out_j)
+    g.gd_predict(cl.ctx)
+    g.gd_force(cl.ctx, empty)
+    with pytest.raises(g.GdError) as e:
+        g.gd_correct(cl.ctx)
+    assert e.value.status == g.GD_ESTATE
+    idx = np.array([0, 5, 999])
+    acc, jrk = _force_gpu(cl, idx)
+    ra, rj = oracle.force(m, x, v, EPS, idx=idx, compensated=True, threads=8)
+    assert rel_err_rows(acc, ra).max() <= F_TOL
+    assert rel_err_rows(jrk, rj).max() <= F_TOL
+    cl.close()
+
+
 @pytest.mark.parametrize("n_act", [1, 2, 7, 64, 100, 513, 1000, 4096])
 def test_force_active_subsets(n_act):
     """Explicit index lists of every size class (each picks a different
