@@ -18,10 +18,12 @@ Roofline: 60 flops per acceleration+jerk pair against the FP64 vector peak.
 The force kernel's per-launch durations come from HIP events that record
 each launch's own start and end (hipExtLaunchKernelGGL) during one more
 integration of the same workload right after the timed steps; in that pass
-the steps are launched directly rather than replayed from a graph, which
-changes the gaps between kernels but not the kernels. The same pass splits
-them by block size (force_by_n_act), and the roofline line also gives the
-fraction reached by the launches with N_act >= 4096.
+the steps are launched directly rather than replayed from a graph (events
+recorded by a captured graph cannot be timed). The kernels are the same, but
+one launched from an idle GPU runs about a fifth longer than inside a replay
+(rocprofv3), so the fraction reported is the lower reading. The same pass
+splits the launches by block size (force_by_n_act), and the roofline line
+also gives the fraction reached by the launches with N_act >= 4096.
 """
 import argparse
 import json
