@@ -379,17 +379,55 @@ __device__ __forceinline__ int wg_append(bool take, int* counter) {
   return pos;
 }
 
+// k_step_correct's view of a context's arrays: the first array of each group
+// that the workspace layout places one stride apart (the state x .. jz, the j
+// stream px .. pvz, the list arrays ix .. ijz), with the two strides. Array k
+// of a group is addressed where it is used (st_arr, pj_arr, il_arr). Passing
+// the 41 pointers of Dev, or computing them all when the kernel starts, left
+// the kernel short of scalar registers: its argument loads came in dependent
+// batches and many values were spilled to vector lanes.
+struct DevC {
+  Sched* sc;
+  double *m, *jm, *st, *pj, *il, *part;
+  long long* tick;
+  unsigned char* lev;
+  int *active, *ilev;
+  long long* tag;
+  long long sn, sl;  // strides in doubles: state and j stream; list arrays
+};
+
+// Array k of the state (x .. jz), j stream (px .. pvz) and list (ix .. ijz)
+// groups, for either view (k is a constant at every use; the j stream has the
+// first six).
+enum : int { kX = 0, kY, kZ, kVx, kVy, kVz, kAx, kAy, kAz, kJx, kJy, kJz };
+__device__ __forceinline__ double* st_arr(const Dev& d, int k) {
+  double* const a[12] = {d.x, d.y, d.z, d.vx, d.vy, d.vz, d.ax, d.ay, d.az, d.jx, d.jy, d.jz};
+  return a[k];
+}
+__device__ __forceinline__ double* pj_arr(const Dev& d, int k) {
+  double* const a[6] = {d.px, d.py, d.pz, d.pvx, d.pvy, d.pvz};
+  return a[k];
+}
+__device__ __forceinline__ double* il_arr(const Dev& d, int k) {
+  double* const a[12] = {d.ix, d.iy, d.iz, d.ivx, d.ivy, d.ivz, d.iax, d.iay, d.iaz, d.ijx, d.ijy, d.ijz};
+  return a[k];
+}
+__device__ __forceinline__ double* st_arr(const DevC& d, int k) { return d.st + k * d.sn; }
+__device__ __forceinline__ double* pj_arr(const DevC& d, int k) { return d.pj + k * d.sn; }
+__device__ __forceinline__ double* il_arr(const DevC& d, int k) { return d.il + k * d.sl; }
+
 // Entry pos of list q: particle j with its predicted state o, its a and jerk
 // at t_i and its level; and j's tag in list q (the block time of the step).
-__device__ __forceinline__ void list_store(const Dev& d, int n, int q, int pos, int j, const double (&o)[6],
+template <class D>
+__device__ __forceinline__ void list_store(const D& d, int n, int q, int pos, int j, const double (&o)[6],
                                            double ax, double ay, double az, double jx, double jy, double jz,
                                            int lv, long long tag) {
   const size_t k = (size_t)q * n + pos;
   d.active[k] = j;
-  d.ix[k] = o[0]; d.iy[k] = o[1]; d.iz[k] = o[2];
-  d.ivx[k] = o[3]; d.ivy[k] = o[4]; d.ivz[k] = o[5];
-  d.iax[k] = ax; d.iay[k] = ay; d.iaz[k] = az;
-  d.ijx[k] = jx; d.ijy[k] = jy; d.ijz[k] = jz;
+  il_arr(d, kX)[k] = o[0]; il_arr(d, kY)[k] = o[1]; il_arr(d, kZ)[k] = o[2];
+  il_arr(d, kVx)[k] = o[3]; il_arr(d, kVy)[k] = o[4]; il_arr(d, kVz)[k] = o[5];
+  il_arr(d, kAx)[k] = ax; il_arr(d, kAy)[k] = ay; il_arr(d, kAz)[k] = az;
+  il_arr(d, kJx)[k] = jx; il_arr(d, kJy)[k] = jy; il_arr(d, kJz)[k] = jz;
   d.ilev[k] = lv;
   d.tag[(size_t)q * n + j] = tag;
 }
@@ -401,12 +439,13 @@ struct PState {
   int lev;
 };
 
-__device__ __forceinline__ PState load_pstate(const Dev& d, int j) {
+template <class D>
+__device__ __forceinline__ PState load_pstate(const D& d, int j) {
   PState p;
-  p.x = d.x[j]; p.y = d.y[j]; p.z = d.z[j];
-  p.vx = d.vx[j]; p.vy = d.vy[j]; p.vz = d.vz[j];
-  p.ax = d.ax[j]; p.ay = d.ay[j]; p.az = d.az[j];
-  p.jx = d.jx[j]; p.jy = d.jy[j]; p.jz = d.jz[j];
+  p.x = st_arr(d, kX)[j]; p.y = st_arr(d, kY)[j]; p.z = st_arr(d, kZ)[j];
+  p.vx = st_arr(d, kVx)[j]; p.vy = st_arr(d, kVy)[j]; p.vz = st_arr(d, kVz)[j];
+  p.ax = st_arr(d, kAx)[j]; p.ay = st_arr(d, kAy)[j]; p.az = st_arr(d, kAz)[j];
+  p.jx = st_arr(d, kJx)[j]; p.jy = st_arr(d, kJy)[j]; p.jz = st_arr(d, kJz)[j];
   p.tick = d.tick[j];
   p.lev = d.lev[j];
   return p;
@@ -414,10 +453,11 @@ __device__ __forceinline__ PState load_pstate(const Dev& d, int j) {
 
 // Particle j (valid) predicted over dt into the j stream (o receives the
 // predicted state).
-__device__ __forceinline__ void predict_store(const Dev& d, int j, double dt, const PState& p, double (&o)[6]) {
+template <class D>
+__device__ __forceinline__ void predict_store(const D& d, int j, double dt, const PState& p, double (&o)[6]) {
   taylor6(dt, p.x, p.y, p.z, p.vx, p.vy, p.vz, p.ax, p.ay, p.az, p.jx, p.jy, p.jz, o);
-  d.px[j] = o[0]; d.py[j] = o[1]; d.pz[j] = o[2];
-  d.pvx[j] = o[3]; d.pvy[j] = o[4]; d.pvz[j] = o[5];
+  pj_arr(d, kX)[j] = o[0]; pj_arr(d, kY)[j] = o[1]; pj_arr(d, kZ)[j] = o[2];
+  pj_arr(d, kVx)[j] = o[3]; pj_arr(d, kVy)[j] = o[4]; pj_arr(d, kVz)[j] = o[5];
 }
 
 // The workgroup's particles [blk * kBlock, (blk + 1) * kBlock) predicted to
@@ -880,8 +920,8 @@ __device__ __forceinline__ bool finite6(const double f[6]) {
 // k_step_correct's other workgroups do the same for the particles this step
 // did not correct (predict_rest). Otherwise the corrector of a step whose
 // list is list 0.
-template <bool kStep>
-__device__ __forceinline__ void correct_body(const Dev& d, const Consts& c, int blk, int nblk, int par = 0,
+template <bool kStep, class D = Dev>
+__device__ __forceinline__ void correct_body(const D& d, const Consts& c, int blk, int nblk, int par = 0,
                                              const PoolStep* step = nullptr) {
   Sched* __restrict__ sc = d.sc;
   const int tid = threadIdx.x;
@@ -907,10 +947,10 @@ __device__ __forceinline__ void correct_body(const Dev& d, const Consts& c, int 
     const int k1 = min(blk * per1 + tid / L1, kcap);
     i = d.active[lo + k1];
     lv = d.ilev[lo + k1];
-    a0[0] = d.iax[lo + k1]; a0[1] = d.iay[lo + k1]; a0[2] = d.iaz[lo + k1];
-    j0[0] = d.ijx[lo + k1]; j0[1] = d.ijy[lo + k1]; j0[2] = d.ijz[lo + k1];
-    xp[0] = d.ix[lo + k1]; xp[1] = d.iy[lo + k1]; xp[2] = d.iz[lo + k1];
-    vp[0] = d.ivx[lo + k1]; vp[1] = d.ivy[lo + k1]; vp[2] = d.ivz[lo + k1];
+    a0[0] = il_arr(d, kAx)[lo + k1]; a0[1] = il_arr(d, kAy)[lo + k1]; a0[2] = il_arr(d, kAz)[lo + k1];
+    j0[0] = il_arr(d, kJx)[lo + k1]; j0[1] = il_arr(d, kJy)[lo + k1]; j0[2] = il_arr(d, kJz)[lo + k1];
+    xp[0] = il_arr(d, kX)[lo + k1]; xp[1] = il_arr(d, kY)[lo + k1]; xp[2] = il_arr(d, kZ)[lo + k1];
+    vp[0] = il_arr(d, kVx)[lo + k1]; vp[1] = il_arr(d, kVy)[lo + k1]; vp[2] = il_arr(d, kVz)[lo + k1];
     if (one_slot) {
       // (lanes past the slices read the last one; their sums are not used)
       const double* o = d.part + (size_t)k1 * c.s1 + min(r1, c.s1 - 1);
@@ -988,10 +1028,10 @@ __device__ __forceinline__ void correct_body(const Dev& d, const Consts& c, int 
       // Loads that do not depend on the reduction, issued with it.
       i = d.active[lo + kk];
       lv = d.ilev[lo + kk];
-      a0[0] = d.iax[lo + kk]; a0[1] = d.iay[lo + kk]; a0[2] = d.iaz[lo + kk];
-      j0[0] = d.ijx[lo + kk]; j0[1] = d.ijy[lo + kk]; j0[2] = d.ijz[lo + kk];
-      xp[0] = d.ix[lo + kk]; xp[1] = d.iy[lo + kk]; xp[2] = d.iz[lo + kk];
-      vp[0] = d.ivx[lo + kk]; vp[1] = d.ivy[lo + kk]; vp[2] = d.ivz[lo + kk];
+      a0[0] = il_arr(d, kAx)[lo + kk]; a0[1] = il_arr(d, kAy)[lo + kk]; a0[2] = il_arr(d, kAz)[lo + kk];
+      j0[0] = il_arr(d, kJx)[lo + kk]; j0[1] = il_arr(d, kJy)[lo + kk]; j0[2] = il_arr(d, kJz)[lo + kk];
+      xp[0] = il_arr(d, kX)[lo + kk]; xp[1] = il_arr(d, kY)[lo + kk]; xp[2] = il_arr(d, kZ)[lo + kk];
+      vp[0] = il_arr(d, kVx)[lo + kk]; vp[1] = il_arr(d, kVy)[lo + kk]; vp[2] = il_arr(d, kVz)[lo + kk];
     }
     double f[6];
     if (first && one_slot) {
@@ -1042,10 +1082,10 @@ __device__ __forceinline__ void correct_body(const Dev& d, const Consts& c, int 
         nl = c.kmax;
         atomicAdd(&bk.clamp, 1);
       }
-      d.x[i] = xn[0]; d.y[i] = xn[1]; d.z[i] = xn[2];
-      d.vx[i] = vn[0]; d.vy[i] = vn[1]; d.vz[i] = vn[2];
-      d.ax[i] = f[0]; d.ay[i] = f[1]; d.az[i] = f[2];
-      d.jx[i] = f[3]; d.jy[i] = f[4]; d.jz[i] = f[5];
+      st_arr(d, kX)[i] = xn[0]; st_arr(d, kY)[i] = xn[1]; st_arr(d, kZ)[i] = xn[2];
+      st_arr(d, kVx)[i] = vn[0]; st_arr(d, kVy)[i] = vn[1]; st_arr(d, kVz)[i] = vn[2];
+      st_arr(d, kAx)[i] = f[0]; st_arr(d, kAy)[i] = f[1]; st_arr(d, kAz)[i] = f[2];
+      st_arr(d, kJx)[i] = f[3]; st_arr(d, kJy)[i] = f[4]; st_arr(d, kJz)[i] = f[5];
       d.tick[i] = t_next;
       d.lev[i] = (unsigned char)nl;
       if (nl != lv) {
@@ -1056,8 +1096,8 @@ __device__ __forceinline__ void correct_body(const Dev& d, const Consts& c, int 
         // the corrected state predicted to the speculated next block time
         taylor6((double)(t_spec - t_next) * c.dt_min, xn[0], xn[1], xn[2], vn[0], vn[1], vn[2], f[0], f[1],
                 f[2], f[3], f[4], f[5], o);
-        d.px[i] = o[0]; d.py[i] = o[1]; d.pz[i] = o[2];
-        d.pvx[i] = o[3]; d.pvy[i] = o[4]; d.pvz[i] = o[5];
+        pj_arr(d, kX)[i] = o[0]; pj_arr(d, kY)[i] = o[1]; pj_arr(d, kZ)[i] = o[2];
+        pj_arr(d, kVx)[i] = o[3]; pj_arr(d, kVy)[i] = o[4]; pj_arr(d, kVz)[i] = o[5];
         take = nl >= kthr_spec;
       }
     }
@@ -1075,7 +1115,8 @@ __device__ __forceinline__ void correct_body(const Dev& d, const Consts& c, int 
 // predicted to the speculated next block time into the j stream, and those
 // active then appended to list par ^ 1. Workgroups take blocks of kBlock
 // particles.
-__device__ __forceinline__ void predict_rest(const Dev& d, const Consts& c, int blk, int nblk, int par) {
+template <class D>
+__device__ __forceinline__ void predict_rest(const D& d, const Consts& c, int blk, int nblk, int par) {
   const Sched* __restrict__ sc = d.sc;
   const int n = c.n, tid = threadIdx.x;
   const int nb = (n + kBlock - 1) / kBlock;
@@ -1122,41 +1163,8 @@ __global__ __launch_bounds__(kBlock) void k_correct(Dev d, Consts c) {
 // are the longer path (every particle's state, the list counter's round
 // trip), and workgroups start in index order (same-box timing of the
 // N = 16384 integration: 548 ms this way, 563 ms the other way round).
-// k_step_correct's view of a context's arrays: the first array of each group
-// that the workspace layout places one stride apart (the state x .. jz, the j
-// stream px .. pvz, the list arrays ix .. ijz), expanded in the kernel. Passing
-// 41 pointers left the kernel short of scalar registers: their loads came in
-// dependent batches and many were spilled to vector lanes.
-struct DevC {
-  Sched* sc;
-  double *m, *jm, *st, *pj, *il, *part;
-  long long* tick;
-  unsigned char* lev;
-  int *active, *ilev;
-  long long* tag;
-  long long sn, sl;  // strides in doubles: state and j stream; list arrays
-};
 
-__device__ __forceinline__ Dev expand(const DevC& e) {
-  Dev d{};
-  d.sc = e.sc; d.m = e.m; d.jm = e.jm;
-  d.x = e.st; d.y = e.st + e.sn; d.z = e.st + 2 * e.sn;
-  d.vx = e.st + 3 * e.sn; d.vy = e.st + 4 * e.sn; d.vz = e.st + 5 * e.sn;
-  d.ax = e.st + 6 * e.sn; d.ay = e.st + 7 * e.sn; d.az = e.st + 8 * e.sn;
-  d.jx = e.st + 9 * e.sn; d.jy = e.st + 10 * e.sn; d.jz = e.st + 11 * e.sn;
-  d.px = e.pj; d.py = e.pj + e.sn; d.pz = e.pj + 2 * e.sn;
-  d.pvx = e.pj + 3 * e.sn; d.pvy = e.pj + 4 * e.sn; d.pvz = e.pj + 5 * e.sn;
-  d.ix = e.il; d.iy = e.il + e.sl; d.iz = e.il + 2 * e.sl;
-  d.ivx = e.il + 3 * e.sl; d.ivy = e.il + 4 * e.sl; d.ivz = e.il + 5 * e.sl;
-  d.iax = e.il + 6 * e.sl; d.iay = e.il + 7 * e.sl; d.iaz = e.il + 8 * e.sl;
-  d.ijx = e.il + 9 * e.sl; d.ijy = e.il + 10 * e.sl; d.ijz = e.il + 11 * e.sl;
-  d.tick = e.tick; d.lev = e.lev; d.active = e.active; d.ilev = e.ilev; d.tag = e.tag;
-  d.part = e.part;
-  return d;
-}
-
-__global__ __launch_bounds__(kBlock) void k_step_correct(DevC dc, Consts c, int par) {
-  const Dev d = expand(dc);
+__global__ __launch_bounds__(kBlock) void k_step_correct(DevC d, Consts c, int par) {
   const int nb = (c.n + kBlock - 1) / kBlock;
   if ((int)blockIdx.x < nb)
     predict_rest(d, c, blockIdx.x, nb, par);
