@@ -177,7 +177,8 @@ gd_status gd_predict(gd_ctx* c, const double* t);
  * and acc/jerk, if given, must hold n rows (the first N_act rows are written,
  * in the order of gd_active).
  * idx != NULL: n_act device int32 indices in [0, n) (repeats allowed); the
- * call synchronises to check them.
+ * call synchronises to check them. n_act = 0 is an empty list: nothing is
+ * computed or written (idx is not read, but must not be NULL).
  * acc, jerk: device (n_act, 3) outputs, or NULL to keep the result internal
  * (as gd_correct needs it). Queues work only when idx == NULL.
  * Errors: GD_ESTATE before any gd_predict, or idx == NULL after gd_predict(t);
